@@ -1,0 +1,132 @@
+/*
+ * bcf.h -- C ABI of the block-compressed neural material decoder for AMD
+ * Instinct MI355X (gfx950).
+ *
+ * Computes the neural material of Weinreich et al., "Real-Time Neural
+ * Materials using Block-Compressed Features" (arXiv 2311.16121):
+ *
+ *     G(u, v, s) = f_eta(T_0(u, v, s_0), ..., T_{n-1}(u, v, s_{n-1}))      eq. (3)
+ *
+ * where every feature pyramid T_i is a mip chain of BC6H blocks (Section 4,
+ * "Block Based Neural Features"; Section 5.2, "Real-time Decoding": the
+ * exported features are mip-mapped BC6 textures and the MLP weights a small
+ * binary buffer), T_i is filtered trilinearly (eq. 9) at s_i = s + b_i
+ * (eq. 10), and f_eta is a ReLU MLP (Section 5.1, "Model structure").
+ *
+ * Conventions for every call:
+ *  - "device" pointers are HIP device memory (e.g. from torch); "host"
+ *    pointers are ordinary process memory read during the call only.
+ *  - The caller owns every buffer. No call allocates device memory.
+ *  - Calls are asynchronous on `stream` (a hipStream_t; NULL = the null
+ *    stream) and never synchronise the host. Kernel faults surface at the
+ *    caller's next synchronisation.
+ *  - A non-OK status leaves a thread-local description in bcf_last_error().
+ *  - All entry points are thread-safe.
+ */
+#ifndef BCF_H
+#define BCF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BCF_ABI_VERSION 1
+
+typedef enum {
+    BCF_OK = 0,
+    BCF_ERR_INVALID_ARG = 1,   /* argument validation failed */
+    BCF_ERR_UNSUPPORTED = 2,   /* valid but outside what the kernels implement */
+    BCF_ERR_DEVICE = 3         /* a HIP runtime call or kernel launch failed */
+} bcf_status;
+
+/* Arithmetic of the decoder MLP f_eta. Fetch, BC6H unpacking (exact integer
+ * work) and trilinear filtering (binary32) are identical in every mode. */
+typedef enum {
+    BCF_FP32 = 0,       /* plain binary32 vector ALU MLP */
+    BCF_FP16 = 1,       /* MFMA, fp16 weights and activations, fp32 accumulation */
+    BCF_BF16 = 2,       /* MFMA, bf16 weights and activations, fp32 accumulation */
+    BCF_FP8 = 3,        /* MFMA, OCP e4m3 with per-layer scales, fp32 accumulation */
+    BCF_FP32_MFMA = 4   /* MFMA on binary32 operands, fp32 accumulation */
+} bcf_precision;
+
+/* One feature pyramid T_i (Section 4.3, "Hardware compliant filtering").
+ * `blocks` (device, 16-byte aligned) holds levels 0..levels-1 back to back.
+ * Level l covers max(width>>l,1) x max(height>>l,1) texels stored as a
+ * row-major grid of 16-byte BC6H blocks (4x4 texels each, texel t of a block
+ * at x = t&3, y = t>>2); a level smaller than 4x4 is one block whose
+ * top-left texels are used. width and height are powers of two;
+ * 1 <= levels <= log2(max(width, height)) + 1. Addressing wraps in u and v.
+ * `lod_bias` is b_i of eq. (10). */
+typedef struct {
+    const void *blocks;
+    uint32_t width, height;
+    uint32_t levels;
+    float lod_bias;
+} bcf_texture;
+
+/* A material: n_textures (1..4) three-channel pyramids whose filtered values
+ * are concatenated in order into the MLP input z0 (eq. 3), and the decoder
+ * f_eta with n_layers (1..4) linear layers of sizes dims[0..n_layers]:
+ * dims[0] == 3 * n_textures, hidden sizes <= 64, output dims[n_layers] <= 16.
+ * ReLU follows every layer but the last. `params` (device, binary32) holds
+ * per layer W[dims[l+1]][dims[l]] row-major, then b[dims[l+1]].
+ * is_signed selects BC6H_SF16 (1) or BC6H_UF16 (0) for every texture. */
+typedef struct {
+    uint32_t n_textures;
+    const bcf_texture *textures;   /* host array [n_textures] */
+    uint32_t n_layers;
+    const uint32_t *dims;          /* host array [n_layers + 1] */
+    const float *params;           /* device */
+    uint32_t is_signed;
+} bcf_material;
+
+/* ABI version of the loaded library (BCF_ABI_VERSION). */
+int bcf_abi_version(void);
+
+/* Thread-local description of the last non-OK status on this thread. */
+const char *bcf_last_error(void);
+
+/* Bytes of a full `levels`-level chain of a width x height BC6H texture,
+ * 16 bytes per 4x4 block (the storage rule behind Table 2's sizes).
+ * Returns 0 for invalid sizes. */
+size_t bcf_texture_bytes(uint32_t width, uint32_t height, uint32_t levels);
+
+/* Workspace for decoding `m` at precision `p`.
+ * Size query: with ws == NULL, writes the required size (bytes, 256-byte
+ * aligned start required) to *ws_bytes and returns.
+ * Fill: with ws != NULL (device) and *ws_bytes >= the size, converts the MLP
+ * parameters into the kernels' padded layout for `p` (rounding to fp16/bf16
+ * or e4m3 with per-layer scales; binary32 stays exact) asynchronously on
+ * `stream`. The workspace also holds scratch used by bcf_decode, so one
+ * workspace serves one decode at a time; the material's textures and params
+ * must not change between prepare and decode without preparing again. */
+bcf_status bcf_prepare(const bcf_material *m, bcf_precision p, void *ws,
+                       size_t *ws_bytes, void *stream);
+
+/* Decode n queries: queries (device, [n][3] binary32 (u, v, s)) ->
+ * out (device, [n][dims[n_layers]] binary32, row-major). s is the scale of
+ * eq. (9) before the per-texture bias. grid_width > 0 declares that the
+ * queries are a row-major image of that many columns (a frame in scanline
+ * order), which lets the decoder share decoded blocks between neighbouring
+ * queries; 0 means no 2D structure. Results do not depend on grid_width.
+ * n == 0 is a no-op. out must not overlap queries, ws or the material.
+ * Non-finite query components produce unspecified values but never an
+ * out-of-bounds access. */
+bcf_status bcf_decode(const bcf_material *m, bcf_precision p, const void *ws,
+                      const float *queries, size_t n, uint32_t grid_width,
+                      float *out, void *stream);
+
+/* Unpack n BC6H blocks (device, [n][16] bytes, 16-byte aligned) to half-float
+ * bit patterns (device, [n][16][3] uint16, texel-major, r g b), bit-exact per
+ * the BC6H format definition (Section 4.2's eqs. (6)-(8) in the format's
+ * integer form). Reserved mode codes decode to zeros. */
+bcf_status bcf_decode_blocks(const void *blocks, size_t n_blocks, uint32_t is_signed,
+                             uint16_t *halves, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -132,8 +132,17 @@ class Material:
         return cls(m.textures, m.res, m.levels, m.dims, m.params, m.lod_bias, m.signed)
 
 
+# Threads used when the caller does not say: the CPUs this process may run on,
+# at most 16 (the host share of one GPU on the GPU machines).
+MAX_THREADS = 16
+
+
+def default_threads() -> int:
+    return max(1, min(MAX_THREADS, len(os.sched_getaffinity(0))))
+
+
 def _threads(n_threads):
-    return n_threads if n_threads else (os.cpu_count() or 1)
+    return n_threads if n_threads else default_threads()
 
 
 def sample(mat: Material, queries: np.ndarray, n_threads: int = 0) -> np.ndarray:

@@ -1,0 +1,178 @@
+"""ctypes binding of libbcf.so (include/bcf.h).
+
+Argument marshalling only: every step of the decode runs in the library's HIP
+kernels. torch provides device memory and the current stream. There is no
+fallback: if the library is missing, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import enum
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIBRARY = os.path.join(PKG, "libbcf.so")
+ABI_VERSION = 1
+
+
+class Precision(enum.IntEnum):
+    FP32 = 0
+    FP16 = 1
+    BF16 = 2
+    FP8 = 3
+    FP32_MFMA = 4
+
+
+class BcfError(RuntimeError):
+    pass
+
+
+class _Texture(C.Structure):
+    _fields_ = [("blocks", C.c_void_p), ("width", C.c_uint32), ("height", C.c_uint32),
+                ("levels", C.c_uint32), ("lod_bias", C.c_float)]
+
+
+class _Material(C.Structure):
+    _fields_ = [("n_textures", C.c_uint32), ("textures", C.POINTER(_Texture)),
+                ("n_layers", C.c_uint32), ("dims", C.POINTER(C.c_uint32)),
+                ("params", C.c_void_p), ("is_signed", C.c_uint32)]
+
+
+def _load():
+    if not os.path.exists(LIBRARY):
+        raise ImportError(f"{LIBRARY} is not built; run `python -m paper_2311_16121_amd.build`")
+    L = C.CDLL(LIBRARY)
+    L.bcf_abi_version.restype = C.c_int
+    L.bcf_last_error.restype = C.c_char_p
+    L.bcf_texture_bytes.restype = C.c_size_t
+    L.bcf_texture_bytes.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32]
+    L.bcf_prepare.restype = C.c_int
+    L.bcf_prepare.argtypes = [C.POINTER(_Material), C.c_int, C.c_void_p, C.POINTER(C.c_size_t), C.c_void_p]
+    L.bcf_decode.restype = C.c_int
+    L.bcf_decode.argtypes = [C.POINTER(_Material), C.c_int, C.c_void_p, C.c_void_p, C.c_size_t,
+                             C.c_uint32, C.c_void_p, C.c_void_p]
+    L.bcf_decode_blocks.restype = C.c_int
+    L.bcf_decode_blocks.argtypes = [C.c_void_p, C.c_size_t, C.c_uint32, C.c_void_p, C.c_void_p]
+    if L.bcf_abi_version() != ABI_VERSION:
+        raise ImportError(f"libbcf ABI {L.bcf_abi_version()}, binding expects {ABI_VERSION}")
+    return L
+
+
+lib = _load()
+
+EXPORTED = ("bcf_abi_version", "bcf_last_error", "bcf_texture_bytes", "bcf_prepare",
+            "bcf_decode", "bcf_decode_blocks")
+
+
+def _check(status: int, what: str):
+    if status != 0:
+        raise BcfError(f"{what}: status {status}: {lib.bcf_last_error().decode()}")
+
+
+def abi_version() -> int:
+    return lib.bcf_abi_version()
+
+
+def texture_bytes(width: int, height: int, levels: int) -> int:
+    return int(lib.bcf_texture_bytes(width, height, levels))
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class Material:
+    """A material on the device: BC6H pyramids + decoder MLP parameters.
+
+    textures: list of uint8 device tensors (each a full level chain)
+    sizes:    list of (width, height) or int (square)
+    levels:   list of level counts
+    dims:     MLP sizes (dims[0] = 3 * len(textures))
+    params:   float32 device tensor, per layer W[out][in] then b[out]
+    """
+
+    def __init__(self, textures, sizes, levels, dims, params, lod_bias=None, signed=False):
+        import torch
+        n = len(textures)
+        self.textures = [t.contiguous() for t in textures]
+        self.params = params.contiguous()
+        for t in self.textures:
+            if t.dtype != torch.uint8 or not t.is_cuda:
+                raise TypeError("textures must be uint8 device tensors")
+        if self.params.dtype != torch.float32 or not self.params.is_cuda:
+            raise TypeError("params must be a float32 device tensor")
+        self.sizes = [(s, s) if isinstance(s, int) else tuple(s) for s in sizes]
+        self.levels = list(levels)
+        self.dims = tuple(int(d) for d in dims)
+        self.signed = bool(signed)
+        bias = list(lod_bias) if lod_bias is not None else [0.0] * n
+        self._tex = (_Texture * n)()
+        for i in range(n):
+            w, h = self.sizes[i]
+            self._tex[i] = _Texture(self.textures[i].data_ptr(), w, h, self.levels[i], float(bias[i]))
+        self._dims = (C.c_uint32 * len(self.dims))(*self.dims)
+        self.c = _Material(n, self._tex, len(self.dims) - 1, self._dims, self.params.data_ptr(),
+                           int(self.signed))
+
+    @classmethod
+    def from_host(cls, textures, sizes, levels, dims, params, lod_bias=None, signed=False,
+                  device="cuda"):
+        import numpy as np
+        import torch
+        tex = [torch.from_numpy(np.ascontiguousarray(t, np.uint8)).to(device) for t in textures]
+        p = torch.from_numpy(np.ascontiguousarray(params, np.float32)).to(device)
+        return cls(tex, sizes, levels, dims, p, lod_bias, signed)
+
+    @property
+    def out_dim(self) -> int:
+        return self.dims[-1]
+
+
+def workspace_bytes(mat: Material, precision=Precision.FP32) -> int:
+    n = C.c_size_t(0)
+    _check(lib.bcf_prepare(C.byref(mat.c), int(precision), None, C.byref(n), None), "bcf_prepare(size)")
+    return n.value
+
+
+def prepare(mat: Material, precision=Precision.FP32, stream=None):
+    """Allocate (torch) and fill the workspace for `precision`."""
+    import torch
+    nbytes = workspace_bytes(mat, precision)
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=mat.params.device)
+    off = (-ws.data_ptr()) % 256
+    ws = ws[off: off + nbytes]
+    n = C.c_size_t(nbytes)
+    _check(lib.bcf_prepare(C.byref(mat.c), int(precision), C.c_void_p(ws.data_ptr()), C.byref(n),
+                           _stream(stream)), "bcf_prepare")
+    return ws
+
+
+def decode(mat: Material, ws, queries, precision=Precision.FP32, grid_width: int = 0, out=None,
+           stream=None):
+    """queries: float32 device tensor [n, 3] (u, v, s) -> out [n, dims[-1]] float32."""
+    import torch
+    q = queries.contiguous()
+    if q.dtype != torch.float32 or q.dim() != 2 or q.shape[1] != 3 or not q.is_cuda:
+        raise TypeError("queries must be a float32 device tensor of shape [n, 3]")
+    n = q.shape[0]
+    if out is None:
+        out = torch.empty((n, mat.out_dim), dtype=torch.float32, device=q.device)
+    _check(lib.bcf_decode(C.byref(mat.c), int(precision), C.c_void_p(ws.data_ptr()),
+                          C.c_void_p(q.data_ptr()), n, grid_width, C.c_void_p(out.data_ptr()),
+                          _stream(stream)), "bcf_decode")
+    return out
+
+
+def decode_blocks(blocks, signed: bool = False, stream=None):
+    """blocks: uint8 device tensor [n, 16] -> int16 device tensor [n, 16, 3] of half bit patterns."""
+    import torch
+    b = blocks.contiguous()
+    if b.dtype != torch.uint8 or not b.is_cuda:
+        raise TypeError("blocks must be a uint8 device tensor")
+    n = b.numel() // 16
+    out = torch.empty((n, 16, 3), dtype=torch.int16, device=b.device)
+    _check(lib.bcf_decode_blocks(C.c_void_p(b.data_ptr()), n, int(signed), C.c_void_p(out.data_ptr()),
+                                 _stream(stream)), "bcf_decode_blocks")
+    return out

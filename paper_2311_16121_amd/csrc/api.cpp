@@ -1,0 +1,268 @@
+// C ABI of the decoder (include/bcf.h): argument validation, workspace layout
+// and kernel dispatch. Every launch goes to the caller's stream; nothing here
+// synchronises or allocates device memory.
+#include "bcf.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "internal.hpp"
+
+namespace {
+
+thread_local std::string g_error;
+
+bcf_status fail(bcf_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return s;
+}
+
+bcf_status device_status(hipError_t e, const char *what)
+{
+    if (e == hipSuccess) return BCF_OK;
+    return fail(BCF_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool is_pow2(uint32_t v) { return v && !(v & (v - 1)); }
+
+uint32_t log2u(uint32_t v)
+{
+    uint32_t r = 0;
+    while (v > 1) { v >>= 1; ++r; }
+    return r;
+}
+
+bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+uint32_t level_dim(uint32_t d, uint32_t l) { return (d >> l) ? (d >> l) : 1u; }
+
+size_t chain_blocks(uint32_t w, uint32_t h, uint32_t levels, uint32_t *per_level_offset)
+{
+    size_t total = 0;
+    for (uint32_t l = 0; l < levels; ++l) {
+        if (per_level_offset) per_level_offset[l] = (uint32_t)total;
+        total += (size_t)((level_dim(w, l) + 3) / 4) * ((level_dim(h, l) + 3) / 4);
+    }
+    return total;
+}
+
+bool kind_of(bcf_precision p, bcf::MlpKind *k)
+{
+    switch (p) {
+    case BCF_FP32: *k = bcf::MLP_VALU_F32; return true;
+    case BCF_FP16: *k = bcf::MLP_MFMA_F16; return true;
+    case BCF_BF16: *k = bcf::MLP_MFMA_BF16; return true;
+    case BCF_FP32_MFMA: *k = bcf::MLP_MFMA_F32; return true;
+    default: return false;
+    }
+}
+
+// Validates the material; fills the kernel descriptors and the padded shape.
+bcf_status describe(const bcf_material *m, bcf::MaterialDesc *d, bcf::MlpShape *sh)
+{
+    if (!m) return fail(BCF_ERR_INVALID_ARG, "material is NULL");
+    if (m->n_textures < 1 || m->n_textures > (uint32_t)bcf::kMaxTextures)
+        return fail(BCF_ERR_INVALID_ARG, "n_textures = %u, expected 1..%d", m->n_textures, bcf::kMaxTextures);
+    if (!m->textures) return fail(BCF_ERR_INVALID_ARG, "textures is NULL");
+    if (m->is_signed > 1) return fail(BCF_ERR_INVALID_ARG, "is_signed = %u, expected 0 or 1", m->is_signed);
+    std::memset(d, 0, sizeof *d);
+    d->n_tex = m->n_textures;
+    d->is_signed = m->is_signed;
+    size_t texel_off = 0;
+    for (uint32_t t = 0; t < m->n_textures; ++t) {
+        const bcf_texture &x = m->textures[t];
+        if (!x.blocks) return fail(BCF_ERR_INVALID_ARG, "texture %u: blocks is NULL", t);
+        if (!aligned(x.blocks, 16)) return fail(BCF_ERR_INVALID_ARG, "texture %u: blocks not 16-byte aligned", t);
+        if (!is_pow2(x.width) || !is_pow2(x.height) || x.width > 32768 || x.height > 32768)
+            return fail(BCF_ERR_INVALID_ARG, "texture %u: %ux%u is not a power-of-two size <= 32768",
+                        t, x.width, x.height);
+        const uint32_t max_levels = log2u(x.width > x.height ? x.width : x.height) + 1;
+        if (x.levels < 1 || x.levels > max_levels)
+            return fail(BCF_ERR_INVALID_ARG, "texture %u: levels = %u, expected 1..%u", t, x.levels, max_levels);
+        if (!std::isfinite(x.lod_bias)) return fail(BCF_ERR_INVALID_ARG, "texture %u: lod_bias not finite", t);
+        bcf::TexDesc &T = d->tex[t];
+        T.blocks = static_cast<const uint4 *>(x.blocks);
+        T.w = x.width;
+        T.h = x.height;
+        T.levels = x.levels;
+        T.bias = x.lod_bias;
+        chain_blocks(x.width, x.height, x.levels, T.blk_off);
+        for (uint32_t l = 0; l < x.levels; ++l) {
+            T.tex_off[l] = (uint32_t)texel_off;
+            texel_off = align_up(texel_off + (size_t)level_dim(x.width, l) * level_dim(x.height, l), 4);
+        }
+        if (texel_off > 0xFFFFFFFFull) return fail(BCF_ERR_UNSUPPORTED, "material too large");
+    }
+    if (m->n_layers < 2 || m->n_layers > 4)
+        return fail(BCF_ERR_UNSUPPORTED, "n_layers = %u, supported 2..4 (1..3 hidden layers)", m->n_layers);
+    if (!m->dims) return fail(BCF_ERR_INVALID_ARG, "dims is NULL");
+    if (!m->params) return fail(BCF_ERR_INVALID_ARG, "params is NULL");
+    if (!aligned(m->params, 4)) return fail(BCF_ERR_INVALID_ARG, "params not 4-byte aligned");
+    if (m->dims[0] != 3 * m->n_textures)
+        return fail(BCF_ERR_INVALID_ARG, "dims[0] = %u, expected 3 * n_textures = %u", m->dims[0], 3 * m->n_textures);
+    uint32_t widest = 0;
+    for (uint32_t l = 1; l < m->n_layers; ++l) {
+        if (m->dims[l] < 1 || m->dims[l] > (uint32_t)bcf::kMaxHidden)
+            return fail(BCF_ERR_UNSUPPORTED, "dims[%u] = %u, hidden sizes must be 1..%d", l, m->dims[l], bcf::kMaxHidden);
+        widest = m->dims[l] > widest ? m->dims[l] : widest;
+    }
+    const uint32_t out = m->dims[m->n_layers];
+    if (out < 1 || out > (uint32_t)bcf::kMaxOut)
+        return fail(BCF_ERR_UNSUPPORTED, "output size %u, supported 1..%d", out, bcf::kMaxOut);
+    std::memset(sh, 0, sizeof *sh);
+    sh->n_layers = m->n_layers;
+    sh->n_hidden = m->n_layers - 1;
+    sh->hidden = widest <= 16 ? 16 : widest <= 32 ? 32 : 64;
+    sh->out = out;
+    for (uint32_t l = 0; l <= m->n_layers; ++l) sh->dims[l] = m->dims[l];
+    return BCF_OK;
+}
+
+size_t scratch_texels(const bcf::MaterialDesc &d)
+{
+    const bcf::TexDesc &T = d.tex[d.n_tex - 1];
+    const uint32_t l = T.levels - 1;
+    return align_up(T.tex_off[l] + (size_t)level_dim(T.w, l) * level_dim(T.h, l), 4);
+}
+
+size_t elem_bytes(bcf::MlpKind k)
+{
+    return (k == bcf::MLP_MFMA_F16 || k == bcf::MLP_MFMA_BF16) ? 2 : k == bcf::MLP_MFMA_FP8 ? 1 : 4;
+}
+
+// Mirrors the operand layouts of the kernels.
+bcf::WsLayout layout(const bcf::MaterialDesc &d, const bcf::MlpShape &sh, bcf::MlpKind k)
+{
+    bcf::WsLayout lay;
+    std::memset(&lay, 0, sizeof lay);
+    size_t off = 256;
+    lay.weights_off = off;
+    const uint32_t L = sh.n_hidden + 1;
+    for (uint32_t l = 0; l < L; ++l) {
+        const uint32_t rows = l < sh.n_hidden ? sh.hidden : (k == bcf::MLP_VALU_F32 ? (sh.out <= 10 ? 10u : 16u) : 16u);
+        size_t elems;
+        if (k == bcf::MLP_VALU_F32) {
+            elems = (size_t)rows * (l == 0 ? 12u : sh.hidden);
+        } else {
+            const uint32_t P = k == bcf::MLP_MFMA_F32 ? 1u : 4u;
+            const uint32_t kc = k == bcf::MLP_MFMA_F32 ? (l == 0 ? 3u : sh.hidden / 4) : (l == 0 ? 1u : sh.hidden / 16);
+            elems = (size_t)(rows / 16) * kc * 64 * P;
+        }
+        lay.layer_w_off[l] = off;
+        off = align_up(off + elems * elem_bytes(k), 256);
+        lay.layer_b_off[l] = off;
+        off = align_up(off + (size_t)rows * 4, 256);
+    }
+    lay.scales_off = off;
+    off = align_up(off + 64, 256);
+    lay.weights_bytes = off - lay.weights_off;
+    lay.scratch_off = off;
+    lay.scratch_bytes = scratch_texels(d) * 8;
+    lay.total = align_up(off + lay.scratch_bytes, 256);
+    return lay;
+}
+
+bcf::PredecodePlan predecode_plan(const bcf::MaterialDesc &d)
+{
+    bcf::PredecodePlan p;
+    std::memset(&p, 0, sizeof p);
+    uint32_t wg = 0;
+    for (uint32_t t = 0; t < d.n_tex; ++t)
+        for (uint32_t l = 0; l < d.tex[t].levels; ++l) {
+            const uint32_t nb = (uint32_t)(((level_dim(d.tex[t].w, l) + 3) / 4) * ((level_dim(d.tex[t].h, l) + 3) / 4));
+            p.seg_tex[p.n_seg] = t;
+            p.seg_lvl[p.n_seg] = l;
+            p.seg_wg[p.n_seg] = wg;
+            wg += (nb + 255) / 256;
+            ++p.n_seg;
+        }
+    p.seg_wg[p.n_seg] = wg;
+    return p;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bcf_abi_version(void) { return BCF_ABI_VERSION; }
+
+const char *bcf_last_error(void) { return g_error.c_str(); }
+
+size_t bcf_texture_bytes(uint32_t width, uint32_t height, uint32_t levels)
+{
+    if (!is_pow2(width) || !is_pow2(height) || width > 32768 || height > 32768) return 0;
+    if (levels < 1 || levels > log2u(width > height ? width : height) + 1) return 0;
+    return 16 * chain_blocks(width, height, levels, nullptr);
+}
+
+bcf_status bcf_prepare(const bcf_material *m, bcf_precision p, void *ws, size_t *ws_bytes, void *stream)
+{
+    bcf::MaterialDesc d;
+    bcf::MlpShape sh;
+    bcf_status st = describe(m, &d, &sh);
+    if (st != BCF_OK) return st;
+    bcf::MlpKind kind;
+    if (!kind_of(p, &kind)) return fail(BCF_ERR_UNSUPPORTED, "precision %d not supported", (int)p);
+    if (!ws_bytes) return fail(BCF_ERR_INVALID_ARG, "ws_bytes is NULL");
+    const bcf::WsLayout lay = layout(d, sh, kind);
+    if (!ws) {
+        *ws_bytes = lay.total;
+        return BCF_OK;
+    }
+    if (*ws_bytes < lay.total)
+        return fail(BCF_ERR_INVALID_ARG, "workspace of %zu bytes, need %zu", *ws_bytes, lay.total);
+    if (!aligned(ws, 256)) return fail(BCF_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+    return device_status(bcf::launch_prepare_weights(m->params, sh, kind, lay, ws,
+                                                     static_cast<hipStream_t>(stream)),
+                         "prepare launch");
+}
+
+bcf_status bcf_decode(const bcf_material *m, bcf_precision p, const void *ws, const float *queries,
+                      size_t n, uint32_t grid_width, float *out, void *stream)
+{
+    bcf::MaterialDesc d;
+    bcf::MlpShape sh;
+    bcf_status st = describe(m, &d, &sh);
+    if (st != BCF_OK) return st;
+    bcf::MlpKind kind;
+    if (!kind_of(p, &kind)) return fail(BCF_ERR_UNSUPPORTED, "precision %d not supported", (int)p);
+    (void)grid_width;
+    if (n == 0) return BCF_OK;
+    if (!ws || !aligned(ws, 256)) return fail(BCF_ERR_INVALID_ARG, "workspace NULL or not 256-byte aligned");
+    if (!queries || !aligned(queries, 4)) return fail(BCF_ERR_INVALID_ARG, "queries NULL or misaligned");
+    if (!out || !aligned(out, 4)) return fail(BCF_ERR_INVALID_ARG, "out NULL or misaligned");
+    if (n > (size_t)1 << 40) return fail(BCF_ERR_UNSUPPORTED, "n = %zu too large", n);
+    const bcf::WsLayout lay = layout(d, sh, kind);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    uint2 *texels = reinterpret_cast<uint2 *>(static_cast<uint8_t *>(const_cast<void *>(ws)) + lay.scratch_off);
+    st = device_status(bcf::launch_predecode(d, predecode_plan(d), texels, s), "predecode launch");
+    if (st != BCF_OK) return st;
+    return device_status(bcf::launch_filter_mlp(d, sh, kind, lay, ws, queries, n, out, s), "decode launch");
+}
+
+bcf_status bcf_decode_blocks(const void *blocks, size_t n_blocks, uint32_t is_signed, uint16_t *halves,
+                             void *stream)
+{
+    if (is_signed > 1) return fail(BCF_ERR_INVALID_ARG, "is_signed = %u, expected 0 or 1", is_signed);
+    if (n_blocks == 0) return BCF_OK;
+    if (!blocks || !aligned(blocks, 16)) return fail(BCF_ERR_INVALID_ARG, "blocks NULL or not 16-byte aligned");
+    if (!halves || !aligned(halves, 16)) return fail(BCF_ERR_INVALID_ARG, "halves NULL or not 16-byte aligned");
+    return device_status(bcf::launch_decode_blocks(static_cast<const uint4 *>(blocks), n_blocks, is_signed,
+                                                   halves, static_cast<hipStream_t>(stream)),
+                         "decode_blocks launch");
+}
+
+}  // extern "C"

@@ -1,0 +1,74 @@
+// Structures shared by the host API (api.cpp) and the kernels (kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace bcf {
+
+constexpr int kMaxTextures = 4;
+constexpr int kMaxLevels = 16;
+constexpr int kMaxHidden = 64;
+constexpr int kMaxOut = 16;
+
+// One feature pyramid as the kernels see it.
+struct TexDesc {
+    const uint4 *blocks;            // level 0 block; levels follow back to back
+    uint32_t w, h, levels;
+    float bias;
+    uint32_t blk_off[kMaxLevels];   // first block of each level
+    uint32_t tex_off[kMaxLevels];   // first texel of each level in the texel scratch
+};
+
+struct MaterialDesc {
+    TexDesc tex[kMaxTextures];
+    uint32_t n_tex;
+    uint32_t is_signed;
+};
+
+// MLP arithmetic variants
+enum MlpKind : uint32_t { MLP_VALU_F32 = 0, MLP_MFMA_F16 = 1, MLP_MFMA_BF16 = 2,
+                          MLP_MFMA_FP8 = 3, MLP_MFMA_F32 = 4 };
+
+// Shapes after padding: every hidden layer has `hidden` units (16, 32 or 64),
+// the output has `out_pad` units (16 for MFMA, `out` rounded for VALU).
+struct MlpShape {
+    uint32_t n_hidden;              // hidden layers (1..3)
+    uint32_t hidden;                // padded hidden width
+    uint32_t out;                   // true output width (<= 16)
+    uint32_t dims[5];               // true dims
+    uint32_t n_layers;
+};
+
+// Workspace: weights of every layer in the kernel layout, then the texel scratch.
+struct WsLayout {
+    size_t weights_off, weights_bytes;
+    size_t layer_w_off[4];          // byte offset of each layer's A-operand / matrix
+    size_t layer_b_off[4];          // byte offset of each layer's fp32 bias (padded)
+    size_t scales_off;              // fp32 per-layer dequantisation scales (fp8)
+    size_t scratch_off, scratch_bytes;
+    size_t total;
+};
+
+// Kernel-side launchers (kernels.hip)
+hipError_t launch_decode_blocks(const uint4 *blocks, size_t n, uint32_t is_signed, uint16_t *out,
+                                hipStream_t s);
+
+struct PredecodePlan {
+    uint32_t n_seg;
+    uint32_t seg_tex[kMaxTextures * kMaxLevels];
+    uint32_t seg_lvl[kMaxTextures * kMaxLevels];
+    uint32_t seg_wg[kMaxTextures * kMaxLevels + 1];     // first workgroup of each segment
+};
+hipError_t launch_predecode(const MaterialDesc &m, const PredecodePlan &p, uint2 *texels,
+                            hipStream_t s);
+
+hipError_t launch_prepare_weights(const float *params, const MlpShape &sh, MlpKind kind,
+                                  const WsLayout &lay, void *ws, hipStream_t s);
+
+hipError_t launch_filter_mlp(const MaterialDesc &m, const MlpShape &sh, MlpKind kind,
+                             const WsLayout &lay, const void *ws, const float *queries, size_t n,
+                             float *out, hipStream_t s);
+
+}  // namespace bcf

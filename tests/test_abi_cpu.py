@@ -1,0 +1,138 @@
+"""The C ABI on the CPU: the library loads, exports every symbol include/bcf.h
+declares, and rejects invalid arguments with status codes before touching the
+GPU (validation never dereferences device pointers, so fake aligned addresses
+suffice here)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def bcf():
+    import paper_2311_16121_amd as bcf
+    return bcf
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "bcf.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bcf_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(bcf):
+    names = declared_functions()
+    assert set(names) == set(bcf.EXPORTED)
+    for name in names:
+        assert hasattr(bcf.lib, name), name
+
+
+def test_abi_version(bcf):
+    assert bcf.abi_version() == 1
+
+
+def test_texture_bytes_matches_oracle_and_rejects_bad_sizes(bcf):
+    for w, h, L in [(2048, 2048, 12), (256, 256, 9), (64, 16, 7), (8, 32, 6), (1, 1, 1), (512, 512, 8)]:
+        assert bcf.texture_bytes(w, h, L) == oracle.texture_bytes(w, h, L)
+    for w, h, L in [(3, 4, 1), (4, 4, 0), (4, 4, 4), (0, 4, 1), (65536, 4, 1)]:
+        assert bcf.texture_bytes(w, h, L) == 0
+
+
+FAKE = 1 << 20          # an aligned, non-null address never dereferenced here
+
+
+def material(bcf, n_tex=4, res=256, levels=9, dims=(12, 16, 16, 9), blocks=FAKE, params=FAKE,
+             signed=0, bias=0.0):
+    from paper_2311_16121_amd._lib import _Material, _Texture
+    tex = (_Texture * max(n_tex, 1))()
+    for i in range(n_tex):
+        w, h = (res, res) if isinstance(res, int) else res
+        tex[i] = _Texture(blocks, w, h, levels, bias)
+    d = (C.c_uint32 * len(dims))(*dims)
+    m = _Material(n_tex, tex, len(dims) - 1, d, params, signed)
+    m._keep = (tex, d)
+    return m
+
+
+def size_query(bcf, m, precision=0):
+    n = C.c_size_t(0)
+    st = bcf.lib.bcf_prepare(C.byref(m), precision, None, C.byref(n), None)
+    return st, n.value, bcf.lib.bcf_last_error().decode()
+
+
+def test_valid_material_size_query(bcf):
+    st, n, _ = size_query(bcf, material(bcf))
+    assert st == 0 and n > 4 * 87381 * 8
+    for p in (1, 2, 4):
+        assert size_query(bcf, material(bcf), p)[0] == 0
+
+
+@pytest.mark.parametrize("kwargs,status,msg", [
+    (dict(n_tex=0), 1, "n_textures"),
+    (dict(n_tex=5, dims=(15, 16, 9)), 1, "n_textures"),
+    (dict(blocks=0), 1, "blocks is NULL"),
+    (dict(blocks=FAKE + 8), 1, "16-byte"),
+    (dict(res=(300, 256)), 1, "power-of-two"),
+    (dict(levels=10), 1, "levels"),
+    (dict(levels=0), 1, "levels"),
+    (dict(dims=(11, 16, 9)), 1, "dims[0]"),
+    (dict(dims=(12, 9)), 2, "n_layers"),
+    (dict(dims=(12, 65, 9)), 2, "hidden"),
+    (dict(dims=(12, 16, 17)), 2, "output"),
+    (dict(params=0), 1, "params"),
+    (dict(signed=2), 1, "is_signed"),
+    (dict(bias=float("nan")), 1, "lod_bias"),
+])
+def test_invalid_materials_are_rejected(bcf, kwargs, status, msg):
+    st, _, err = size_query(bcf, material(bcf, **kwargs))
+    assert st == status
+    assert msg in err
+
+
+def test_unsupported_precision_and_null_arguments(bcf):
+    m = material(bcf)
+    st, _, err = size_query(bcf, m, 3)
+    assert st == 2 and "precision" in err
+    assert size_query(bcf, m, 99)[0] == 2
+    assert bcf.lib.bcf_prepare(None, 0, None, C.byref(C.c_size_t()), None) == 1
+    assert bcf.lib.bcf_prepare(C.byref(m), 0, None, None, None) == 1
+    # workspace too small / misaligned
+    n = C.c_size_t(100)
+    assert bcf.lib.bcf_prepare(C.byref(m), 0, C.c_void_p(FAKE), C.byref(n), None) == 1
+    assert "workspace" in bcf.lib.bcf_last_error().decode()
+    n = C.c_size_t(1 << 40)
+    assert bcf.lib.bcf_prepare(C.byref(m), 0, C.c_void_p(FAKE + 16), C.byref(n), None) == 1
+    # decode: n == 0 is a no-op that touches nothing
+    assert bcf.lib.bcf_decode(C.byref(m), 0, None, None, 0, 0, None, None) == 0
+    assert bcf.lib.bcf_decode(C.byref(m), 0, None, C.c_void_p(FAKE), 5, 0, C.c_void_p(FAKE), None) == 1
+    assert bcf.lib.bcf_decode(C.byref(m), 0, C.c_void_p(FAKE), None, 5, 0, C.c_void_p(FAKE), None) == 1
+    assert bcf.lib.bcf_decode(C.byref(m), 0, C.c_void_p(FAKE), C.c_void_p(FAKE), 5, 0, None, None) == 1
+    assert bcf.lib.bcf_decode(C.byref(m), 0, C.c_void_p(FAKE), C.c_void_p(FAKE + 2), 5, 0,
+                              C.c_void_p(FAKE), None) == 1
+    # decode_blocks
+    assert bcf.lib.bcf_decode_blocks(None, 0, 0, None, None) == 0
+    assert bcf.lib.bcf_decode_blocks(None, 4, 0, C.c_void_p(FAKE), None) == 1
+    assert bcf.lib.bcf_decode_blocks(C.c_void_p(FAKE + 4), 4, 0, C.c_void_p(FAKE), None) == 1
+    assert bcf.lib.bcf_decode_blocks(C.c_void_p(FAKE), 4, 2, C.c_void_p(FAKE), None) == 1
+
+
+def test_error_text_is_thread_local(bcf):
+    import threading
+    size_query(bcf, material(bcf, n_tex=0))
+    seen = {}
+
+    def other():
+        size_query(bcf, material(bcf, levels=0))
+        seen["other"] = bcf.lib.bcf_last_error().decode()
+
+    t = threading.Thread(target=other)
+    t.start()
+    t.join()
+    assert "levels" in seen["other"]
+    assert "n_textures" in bcf.lib.bcf_last_error().decode()

@@ -1,0 +1,69 @@
+"""The GPU library's BC6H unpacking logic, compiled for the host, against the
+oracle: bit-exact on every mode, reserved codes, and signed blocks.
+
+This checks the kernel's integer decode on the CPU before any GPU run; the
+GPU parity tests repeat the comparison on the device build.
+"""
+import ctypes as C
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+SRC = os.path.join(HERE, "host_shim", "bc6h_host_shim.cpp")
+OUT = os.path.join(HERE, "host_shim", "_build", "libbc6h_host_shim.so")
+HIPCC = "/opt/rocm/bin/hipcc"
+
+
+@pytest.fixture(scope="module")
+def shim():
+    if not os.path.exists(HIPCC):
+        pytest.skip("hipcc not available")
+    deps = [SRC, os.path.join(ROOT, "paper_2311_16121_amd", "csrc", "bc6h_device.hpp")]
+    if not os.path.exists(OUT) or os.path.getmtime(OUT) < max(os.path.getmtime(d) for d in deps):
+        os.makedirs(os.path.dirname(OUT), exist_ok=True)
+        subprocess.run([HIPCC, "-O2", "-std=c++17", "-shared", "-fPIC",
+                        "-I", os.path.join(ROOT, "paper_2311_16121_amd", "csrc"), SRC, "-o", OUT],
+                       check=True, stderr=subprocess.DEVNULL)
+    L = C.CDLL(OUT)
+    L.shim_decode_blocks.argtypes = [C.c_void_p, C.c_size_t, C.c_int, C.c_void_p]
+    return L
+
+
+def run(shim, blocks, signed):
+    b = np.ascontiguousarray(blocks, np.uint8)
+    out = np.zeros((b.shape[0], 16, 3), np.uint16)
+    shim.shim_decode_blocks(b.ctypes.data, b.shape[0], int(signed), out.ctypes.data)
+    return out
+
+
+@pytest.mark.parametrize("signed", [False, True])
+def test_random_blocks_every_mode(shim, signed):
+    g = synth.rng(1000 + signed)
+    blocks = np.concatenate([synth.random_mode_blocks(60000, g), synth.reserved_blocks(2000, g),
+                             synth.bounded_blocks(20000, g)])
+    got = run(shim, blocks, signed)
+    ref = oracle.decode_blocks(blocks, signed)
+    bad = np.nonzero((got != ref).any(axis=(1, 2)))[0]
+    assert len(bad) == 0, [(int(i), oracle.block_fields(blocks[i].tobytes())["mode"]) for i in bad[:10]]
+
+
+@pytest.mark.parametrize("mode", range(1, 15))
+def test_single_bit_flips(shim, mode):
+    g = synth.rng(1100 + mode)
+    base = synth.bounded_blocks(32, g, modes=(mode,))
+    flips = []
+    for p in range(128):
+        b = base.copy()
+        b[:, p >> 3] ^= np.uint8(1 << (p & 7))
+        flips.append(b)
+    blocks = np.concatenate(flips)
+    for signed in (False, True):
+        assert np.array_equal(run(shim, blocks, signed), oracle.decode_blocks(blocks, signed))
