@@ -8,10 +8,13 @@ texel is below 1.0), decoder MLP 12-32-32-10, and the 3840x2160 queries of a
 perspective ground plane in scanline order with LOD from analytic uv
 derivatives. Synthetic seeded data; no trained weights exist for it.
 
-One step = one bcf_decode of the whole frame with textures, MLP and queries
-already resident in HBM. The headline value is the FP16-MFMA rate; the plain
-FP32 rate is timed on the same inputs, and both are checked against the CPU
-oracle on a seeded sample of queries (FP16 bar: 2e-3 absolute).
+One step = one decode of the whole frame with textures, MLP and queries
+already resident in HBM, issued as its two calls (bcf_unpack, then
+bcf_decode_unpacked) so that HIP events time each kernel. The headline value is the FP16-MFMA rate; the plain
+FP32 rate is timed on the same inputs. The FP16 output is compared with the
+FP32 output over the whole frame (the GPU parity tests pin the FP32 path to
+the fp64 oracle within 1e-5 on this workload, and FP16 within 2e-3); the rate
+is reported only when that difference stays within 2e-3.
 
 Prints one JSON line.
 """
@@ -36,17 +39,18 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def unique_blocks(textures, queries):
-    """Number of distinct (texture, level, block) the trilinear footprints of
-    `queries` touch: the blocks a decode must read at least once."""
+def _footprints(textures, queries):
+    """For each distinct pyramid geometry ((w, h), levels, bias) and each level:
+    how many pyramids share it, the level's size, and the integer tap
+    coordinates (x0, y0) of every query footprint that reads the level
+    (eq. 9 at s_i = s + b_i, texel centres at (i + 1/2)/w, wrap addressing)."""
     u = queries[:, 0].astype(np.float64)
     v = queries[:, 1].astype(np.float64)
     s = queries[:, 2].astype(np.float64)
     u -= np.floor(u)
     v -= np.floor(v)
-    total = 0
     counts = {}
-    for t in textures:                      # identical pyramids touch identical blocks
+    for t in textures:                      # pyramids of one geometry touch the same positions
         counts[t] = counts.get(t, 0) + 1
     for ((w0, h0), levels, bias), times in counts.items():
         si = np.clip(s + bias, 0, levels - 1)
@@ -54,24 +58,85 @@ def unique_blocks(textures, queries):
         l1 = np.minimum(l0 + 1, levels - 1)
         for lev in range(levels):
             w, h = max(w0 >> lev, 1), max(h0 >> lev, 1)
-            bx, by = (w + 3) // 4, (h + 3) // 4
             sel = (l0 == lev) | (l1 == lev)
             if not sel.any():
                 continue
             x0 = np.floor(u[sel] * w - 0.5).astype(np.int64)
             y0 = np.floor(v[sel] * h - 0.5).astype(np.int64)
-            mark = np.zeros(bx * by, bool)
-            for dx in (0, 1):
-                for dy in (0, 1):
-                    mark[(((y0 + dy) % h) // 4) * bx + ((x0 + dx) % w) // 4] = True
-            total += times * int(mark.sum())
+            yield times, w, h, x0, y0
+
+
+def unique_blocks(textures, queries):
+    """Distinct (pyramid, level, block) the trilinear footprints of `queries`
+    touch: the BC6H blocks a decode must read at least once."""
+    total = 0
+    for times, w, h, x0, y0 in _footprints(textures, queries):
+        bx, by = (w + 3) // 4, (h + 3) // 4
+        mark = np.zeros(bx * by, bool)
+        for dx in (0, 1):
+            for dy in (0, 1):
+                mark[(((y0 + dy) % h) // 4) * bx + ((x0 + dx) % w) // 4] = True
+        total += times * int(mark.sum())
     return total
 
 
-def cpu_baseline(host_mat, queries, budget_s):
-    """The oracle on a bounded seeded sample of the workload's queries."""
+def unique_texels(textures, queries):
+    """Distinct (pyramid, level, texel) the footprints touch: the unpacked
+    texels the filter kernel must read at least once."""
+    total = 0
+    for times, w, h, x0, y0 in _footprints(textures, queries):
+        mark = np.zeros(w * h, bool)
+        for dx in (0, 1):
+            for dy in (0, 1):
+                mark[((y0 + dy) % h) * w + (x0 + dx) % w] = True
+        total += times * int(mark.sum())
+    return total
+
+
+def all_blocks(textures):
+    return sum(sum(((max(w >> l, 1) + 3) // 4) * ((max(h >> l, 1) + 3) // 4) for l in range(L))
+               for (w, h), L, _ in textures)
+
+
+def sources_digest():
+    """Digest of the library's sources: counter figures taken from another
+    build of the kernels do not apply."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2311_16121_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".hpp", ".cpp", ".h")):
+            h.update(name.encode())
+            h.update(open(os.path.join(csrc, name), "rb").read())
+    return h.hexdigest()[:16]
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_frame_fp16_frame4k_traffic.md")
+
+
+def measured_traffic():
+    """HBM bytes per k_frame (FP16) launch from the committed counter summary,
+    or None when it is missing or was taken from other kernel sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    fields = {}
+    for line in open(TRAFFIC_FILE):
+        if line.startswith("- ") and ":" in line:
+            k, v = line[2:].split(":", 1)
+            fields[k.strip()] = v.strip().strip("`")
+    if fields.get("sources_digest") != sources_digest():
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(material, queries, budget_s):
+    """The CPU oracle timed on a bounded seeded sample of the workload's queries."""
     import oracle
     import synth
+    host_mat = oracle.Material.from_synth(material)
     threads = oracle.default_threads()
     pick = synth.rng(synth.SEED_SHUFFLE).permutation(len(queries))
     n = 2048
@@ -94,7 +159,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--err-sample", type=int, default=16384)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="first run a plain copy of this many MiB (to scale memory counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -103,7 +169,6 @@ def main():
 
     import torch
 
-    import oracle
     import paper_2311_16121_amd as bcf
     import synth
 
@@ -121,36 +186,62 @@ def main():
     stream = torch.cuda.current_stream()
 
     def run(p, steps):
+        """`steps` whole decodes, each as its two calls (unpack, then filter +
+        MLP) with HIP events around each on the launch stream."""
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
         start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         start.record(stream)
-        for _ in range(steps):
-            bcf.decode(mat, ws[p], qd, p, grid_width=3840, out=out[p])
+        for e in ev:
+            e[0].record(stream)
+            bcf.unpack(mat, ws[p], stream)
+            e[1].record(stream)
+            bcf.decode_unpacked(mat, ws[p], qd, p, grid_width=3840, out=out[p], stream=stream)
+            e[2].record(stream)
         end.record(stream)
         torch.cuda.synchronize()
-        return start.elapsed_time(end) / steps
+        unpack_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / steps
+        frame_ms = sum(e[1].elapsed_time(e[2]) for e in ev) / steps
+        return start.elapsed_time(end) / steps, unpack_ms, frame_ms
+
+    if args.copy_probe:
+        # a plain copy of known size, for scaling memory counters (profiling runs only)
+        src = torch.ones(args.copy_probe << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        log(f"copy probe: {args.copy_probe} MiB read, {args.copy_probe} MiB written")
+        del src, dst
 
     log("warmup")
     for p in out:
         run(p, args.warmup)
     log("timing")
-    ms = {p: run(p, args.steps) for p in out}
+    t = {p: run(p, args.steps) for p in out}
+    ms = {p: t[p][0] for p in out}
     qps = {p: n / (ms[p] * 1e-3) for p in out}
 
-    # accuracy on a seeded sample of the frame
-    host = oracle.Material.from_synth(m)
-    pick = np.sort(synth.rng(99).choice(n, size=min(args.err_sample, n), replace=False))
-    ref = oracle.decode(host, q[pick])
-    err = {p: float(np.abs(out[p][torch.from_numpy(pick).cuda()].cpu().numpy() - ref).max()) for p in out}
+    # FP16 against FP32 over the whole frame
+    p16, p32 = bcf.Precision.FP16, bcf.Precision.FP32
+    diff16 = float((out[p16] - out[p32]).abs().max().item())
 
-    # roofline: algorithmic HBM bytes = queries in + outputs out + every touched block once
-    U = unique_blocks([((r, r), L, b) for r, L, b in zip(m.res, m.levels, m.lod_bias)], q)
-    alg_bytes = n * 12 + n * 4 * m.dims[-1] + 16 * U
-    p16 = bcf.Precision.FP16
-    achieved = alg_bytes / (ms[p16] * 1e-3) / 1e9
+    # algorithmic HBM bytes (every byte a decode must move at least once)
+    geo = [((r, r), L, b) for r, L, b in zip(m.res, m.levels, m.lod_bias)]
+    c = m.dims[-1]
+    U, T, NB = unique_blocks(geo, q), unique_texels(geo, q), all_blocks(geo)
+    frame_bytes = n * 12 + n * 4 * c + 8 * T            # queries, outputs, touched texels
+    unpack_bytes = NB * (16 + 16 * 8)                   # every block in, its 16 texels out
+    step_bytes = n * 12 + n * 4 * c + 16 * U            # the whole path: queries, outputs, touched blocks
+
+    def roof(kernel, nbytes, kms, traffic=None):
+        achieved = nbytes / (kms * 1e-3) / 1e9
+        return {"bound": "hbm", "kernel": kernel, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "alg_bytes_per_launch": nbytes,
+                "launch_ms": kms}
+
     line = {
         "metric": METRIC,
-        "value": qps[p16] if err[p16] <= 2e-3 else None,
+        "value": qps[p16] if diff16 <= 2e-3 else None,
         "unit": "queries/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -168,26 +259,21 @@ def main():
             "grid_width": 3840,
             "precision": "fp16 MFMA MLP, fp32 filter, exact integer BC6H",
         },
-        "fp16_max_abs_err": err[p16],
-        "fp32_value": qps[bcf.Precision.FP32],
-        "fp32_ms_per_step": ms[bcf.Precision.FP32],
-        "fp32_max_abs_err": err[bcf.Precision.FP32],
-        "err_sample": int(len(pick)),
-        "roofline": {
-            "bound": "hbm",
-            "kernel": "whole decode step",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
-            "alg_bytes_per_launch": alg_bytes,
-            "unique_blocks": U,
+        "fp16_max_abs_diff_vs_fp32": diff16,
+        "fp32_value": qps[p32],
+        "fp32_ms_per_step": ms[p32],
+        # the dominant kernel: filter + MLP from the unpacked texels (FP16 MLP)
+        "roofline": roof("k_frame (fp16)", frame_bytes, t[p16][2], measured_traffic()),
+        "kernels": {
+            "unpack": roof("k_predecode", unpack_bytes, t[p16][1]),
+            "frame_fp32": roof("k_frame (fp32)", frame_bytes, t[p32][2]),
+            "step_fp16": roof("whole step", step_bytes, ms[p16]),
         },
+        "counts": {"unique_blocks": U, "unique_texels": T, "all_blocks": NB},
     }
     if not args.no_cpu_baseline:
         log("cpu baseline")
-        line["cpu_baseline"] = cpu_baseline(host, q, args.cpu_budget)
+        line["cpu_baseline"] = cpu_baseline(m, q, args.cpu_budget)
     print(json.dumps(line), flush=True)
 
 

@@ -48,7 +48,8 @@ typedef enum {
     BCF_FP32 = 0,       /* plain binary32 vector ALU MLP */
     BCF_FP16 = 1,       /* MFMA, fp16 weights and activations, fp32 accumulation */
     BCF_BF16 = 2,       /* MFMA, bf16 weights and activations, fp32 accumulation */
-    BCF_FP8 = 3,        /* MFMA, OCP e4m3 with per-layer scales, fp32 accumulation */
+    BCF_FP8 = 3,        /* MFMA, OCP e4m3 weights and activations with per-layer
+                           scales, fp32 accumulation; needs act_absmax */
     BCF_FP32_MFMA = 4   /* MFMA on binary32 operands, fp32 accumulation */
 } bcf_precision;
 
@@ -69,11 +70,14 @@ typedef struct {
 
 /* A material: n_textures (1..4) three-channel pyramids whose filtered values
  * are concatenated in order into the MLP input z0 (eq. 3), and the decoder
- * f_eta with n_layers (1..4) linear layers of sizes dims[0..n_layers]:
+ * f_eta with n_layers (2..4) linear layers of sizes dims[0..n_layers]:
  * dims[0] == 3 * n_textures, hidden sizes <= 64, output dims[n_layers] <= 16.
  * ReLU follows every layer but the last. `params` (device, binary32) holds
  * per layer W[dims[l+1]][dims[l]] row-major, then b[dims[l+1]].
- * is_signed selects BC6H_SF16 (1) or BC6H_UF16 (0) for every texture. */
+ * is_signed selects BC6H_SF16 (1) or BC6H_UF16 (0) for every texture.
+ * act_absmax (device, n_layers floats, or NULL) is the largest magnitude of
+ * each layer's input over a calibration batch (bcf_calibrate); only BCF_FP8
+ * reads it, to fix its static per-layer activation scales. */
 typedef struct {
     uint32_t n_textures;
     const bcf_texture *textures;   /* host array [n_textures] */
@@ -81,6 +85,7 @@ typedef struct {
     const uint32_t *dims;          /* host array [n_layers + 1] */
     const float *params;           /* device */
     uint32_t is_signed;
+    const float *act_absmax;       /* device, may be NULL */
 } bcf_material;
 
 /* ABI version of the loaded library (BCF_ABI_VERSION). */
@@ -100,9 +105,10 @@ size_t bcf_texture_bytes(uint32_t width, uint32_t height, uint32_t levels);
  * Fill: with ws != NULL (device) and *ws_bytes >= the size, converts the MLP
  * parameters into the kernels' padded layout for `p` (rounding to fp16/bf16
  * or e4m3 with per-layer scales; binary32 stays exact) asynchronously on
- * `stream`. The workspace also holds scratch used by bcf_decode, so one
- * workspace serves one decode at a time; the material's textures and params
- * must not change between prepare and decode without preparing again. */
+ * `stream`. The workspace also holds the texel scratch that bcf_unpack
+ * writes and the decode reads, so one workspace serves one decode at a time;
+ * the material's params must not change between prepare and decode without
+ * preparing again, nor its textures without unpacking again. */
 bcf_status bcf_prepare(const bcf_material *m, bcf_precision p, void *ws,
                        size_t *ws_bytes, void *stream);
 
@@ -110,14 +116,39 @@ bcf_status bcf_prepare(const bcf_material *m, bcf_precision p, void *ws,
  * out (device, [n][dims[n_layers]] binary32, row-major). s is the scale of
  * eq. (9) before the per-texture bias. grid_width > 0 declares that the
  * queries are a row-major image of that many columns (a frame in scanline
- * order), which lets the decoder share decoded blocks between neighbouring
- * queries; 0 means no 2D structure. Results do not depend on grid_width.
+ * order); 0 means no 2D structure. Results do not depend on grid_width.
  * n == 0 is a no-op. out must not overlap queries, ws or the material.
  * Non-finite query components produce unspecified values but never an
- * out-of-bounds access. */
-bcf_status bcf_decode(const bcf_material *m, bcf_precision p, const void *ws,
+ * out-of-bounds access. Same as bcf_unpack followed by bcf_decode_unpacked
+ * on `stream`; ws (prepared for `p`) receives the unpacked texels. */
+bcf_status bcf_decode(const bcf_material *m, bcf_precision p, void *ws,
                       const float *queries, size_t n, uint32_t grid_width,
                       float *out, void *stream);
+
+/* First half of bcf_decode: unpacks every BC6H block of every level of every
+ * pyramid (Section 4.2, eqs. (6)-(8) in the format's integer form) into the
+ * texel scratch of ws (device, prepared for this material at any precision;
+ * the scratch layout does not depend on the precision). The texels stay valid
+ * until the textures change, so a material drawn several times between
+ * texture updates needs one unpack. */
+bcf_status bcf_unpack(const bcf_material *m, void *ws, void *stream);
+
+/* Second half of bcf_decode: trilinear filtering (eqs. (9), (10)) of the
+ * texels a previous bcf_unpack of this material left in ws, and the MLP
+ * (eq. (3)), with bcf_decode's arguments and results. ws must have been
+ * prepared for `p` and unpacked, in stream order, before this call. */
+bcf_status bcf_decode_unpacked(const bcf_material *m, bcf_precision p, const void *ws,
+                               const float *queries, size_t n, uint32_t grid_width,
+                               float *out, void *stream);
+
+/* Calibration for BCF_FP8 (Section 5.2 stores the MLP weights in a reduced
+ * precision; fp8 also quantises activations, with static per-layer scales):
+ * decodes n queries (device, [n][3]) with the plain fp32 path and writes to
+ * act_absmax (device, n_layers floats) the largest magnitude each layer's
+ * input reaches. `ws` must be a workspace prepared for BCF_FP32 for this
+ * material (its texel scratch is overwritten). */
+bcf_status bcf_calibrate(const bcf_material *m, void *ws, const float *queries, size_t n,
+                         float *act_absmax, void *stream);
 
 /* Unpack n BC6H blocks (device, [n][16] bytes, 16-byte aligned) to half-float
  * bit patterns (device, [n][16][3] uint16, texel-major, r g b), bit-exact per

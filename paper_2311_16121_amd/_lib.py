@@ -35,12 +35,12 @@ class _Texture(C.Structure):
 class _Material(C.Structure):
     _fields_ = [("n_textures", C.c_uint32), ("textures", C.POINTER(_Texture)),
                 ("n_layers", C.c_uint32), ("dims", C.POINTER(C.c_uint32)),
-                ("params", C.c_void_p), ("is_signed", C.c_uint32)]
+                ("params", C.c_void_p), ("is_signed", C.c_uint32), ("act_absmax", C.c_void_p)]
 
 
 def _load():
     if not os.path.exists(LIBRARY):
-        raise ImportError(f"{LIBRARY} is not built; run `python -m paper_2311_16121_amd.build`")
+        raise ImportError(f"{LIBRARY} is not built; run `python paper_2311_16121_amd/build.py`")
     L = C.CDLL(LIBRARY)
     L.bcf_abi_version.restype = C.c_int
     L.bcf_last_error.restype = C.c_char_p
@@ -51,6 +51,14 @@ def _load():
     L.bcf_decode.restype = C.c_int
     L.bcf_decode.argtypes = [C.POINTER(_Material), C.c_int, C.c_void_p, C.c_void_p, C.c_size_t,
                              C.c_uint32, C.c_void_p, C.c_void_p]
+    L.bcf_unpack.restype = C.c_int
+    L.bcf_unpack.argtypes = [C.POINTER(_Material), C.c_void_p, C.c_void_p]
+    L.bcf_decode_unpacked.restype = C.c_int
+    L.bcf_decode_unpacked.argtypes = [C.POINTER(_Material), C.c_int, C.c_void_p, C.c_void_p, C.c_size_t,
+                                      C.c_uint32, C.c_void_p, C.c_void_p]
+    L.bcf_calibrate.restype = C.c_int
+    L.bcf_calibrate.argtypes = [C.POINTER(_Material), C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p,
+                                C.c_void_p]
     L.bcf_decode_blocks.restype = C.c_int
     L.bcf_decode_blocks.argtypes = [C.c_void_p, C.c_size_t, C.c_uint32, C.c_void_p, C.c_void_p]
     if L.bcf_abi_version() != ABI_VERSION:
@@ -61,7 +69,7 @@ def _load():
 lib = _load()
 
 EXPORTED = ("bcf_abi_version", "bcf_last_error", "bcf_texture_bytes", "bcf_prepare",
-            "bcf_decode", "bcf_decode_blocks")
+            "bcf_decode", "bcf_unpack", "bcf_decode_unpacked", "bcf_calibrate", "bcf_decode_blocks")
 
 
 def _check(status: int, what: str):
@@ -113,8 +121,18 @@ class Material:
             w, h = self.sizes[i]
             self._tex[i] = _Texture(self.textures[i].data_ptr(), w, h, self.levels[i], float(bias[i]))
         self._dims = (C.c_uint32 * len(self.dims))(*self.dims)
+        self.act_absmax = None
         self.c = _Material(n, self._tex, len(self.dims) - 1, self._dims, self.params.data_ptr(),
-                           int(self.signed))
+                           int(self.signed), None)
+
+    def set_act_absmax(self, absmax):
+        """Per-layer largest input magnitudes (device float32 [n_layers]) for BCF_FP8."""
+        import torch
+        a = absmax.contiguous()
+        if a.dtype != torch.float32 or not a.is_cuda or a.numel() != len(self.dims) - 1:
+            raise TypeError("act_absmax must be a float32 device tensor with one entry per layer")
+        self.act_absmax = a
+        self.c.act_absmax = a.data_ptr()
 
     @classmethod
     def from_host(cls, textures, sizes, levels, dims, params, lod_bias=None, signed=False,
@@ -149,20 +167,61 @@ def prepare(mat: Material, precision=Precision.FP32, stream=None):
     return ws
 
 
-def decode(mat: Material, ws, queries, precision=Precision.FP32, grid_width: int = 0, out=None,
-           stream=None):
-    """queries: float32 device tensor [n, 3] (u, v, s) -> out [n, dims[-1]] float32."""
+def _queries(queries):
     import torch
     q = queries.contiguous()
     if q.dtype != torch.float32 or q.dim() != 2 or q.shape[1] != 3 or not q.is_cuda:
         raise TypeError("queries must be a float32 device tensor of shape [n, 3]")
-    n = q.shape[0]
+    return q
+
+
+def _out(mat: Material, q, out):
+    import torch
     if out is None:
-        out = torch.empty((n, mat.out_dim), dtype=torch.float32, device=q.device)
+        return torch.empty((q.shape[0], mat.out_dim), dtype=torch.float32, device=q.device)
+    if (out.dtype != torch.float32 or not out.is_cuda or not out.is_contiguous()
+            or tuple(out.shape) != (q.shape[0], mat.out_dim)):
+        raise TypeError(f"out must be a contiguous float32 device tensor of shape [{q.shape[0]}, {mat.out_dim}]")
+    return out
+
+
+def decode(mat: Material, ws, queries, precision=Precision.FP32, grid_width: int = 0, out=None,
+           stream=None):
+    """queries: float32 device tensor [n, 3] (u, v, s) -> out [n, dims[-1]] float32."""
+    q = _queries(queries)
+    out = _out(mat, q, out)
     _check(lib.bcf_decode(C.byref(mat.c), int(precision), C.c_void_p(ws.data_ptr()),
-                          C.c_void_p(q.data_ptr()), n, grid_width, C.c_void_p(out.data_ptr()),
+                          C.c_void_p(q.data_ptr()), q.shape[0], grid_width, C.c_void_p(out.data_ptr()),
                           _stream(stream)), "bcf_decode")
     return out
+
+
+def unpack(mat: Material, ws, stream=None):
+    """Unpack every block of the material into the texel scratch of `ws`."""
+    _check(lib.bcf_unpack(C.byref(mat.c), C.c_void_p(ws.data_ptr()), _stream(stream)), "bcf_unpack")
+
+
+def decode_unpacked(mat: Material, ws, queries, precision=Precision.FP32, grid_width: int = 0, out=None,
+                    stream=None):
+    """decode() from the texels a previous unpack() left in `ws`."""
+    q = _queries(queries)
+    out = _out(mat, q, out)
+    _check(lib.bcf_decode_unpacked(C.byref(mat.c), int(precision), C.c_void_p(ws.data_ptr()),
+                                   C.c_void_p(q.data_ptr()), q.shape[0], grid_width,
+                                   C.c_void_p(out.data_ptr()), _stream(stream)), "bcf_decode_unpacked")
+    return out
+
+
+def calibrate(mat: Material, queries, stream=None):
+    """Largest input magnitude of every MLP layer over `queries` (plain fp32
+    decode); returns a float32 device tensor [n_layers] for set_act_absmax."""
+    import torch
+    q = _queries(queries)
+    ws = prepare(mat, Precision.FP32, stream)
+    absmax = torch.empty(len(mat.dims) - 1, dtype=torch.float32, device=q.device)
+    _check(lib.bcf_calibrate(C.byref(mat.c), C.c_void_p(ws.data_ptr()), C.c_void_p(q.data_ptr()),
+                             q.shape[0], C.c_void_p(absmax.data_ptr()), _stream(stream)), "bcf_calibrate")
+    return absmax
 
 
 def decode_blocks(blocks, signed: bool = False, stream=None):

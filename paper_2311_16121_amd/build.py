@@ -1,6 +1,9 @@
 """Compile the HIP library (libbcf.so) in-tree for gfx950.
 
-    python -m paper_2311_16121_amd.build
+    python paper_2311_16121_amd/build.py [-v]
+
+Runs as a script (or loaded by file path), never through the package, whose
+import needs the library this builds.
 """
 from __future__ import annotations
 
@@ -13,26 +16,38 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIBRARY = os.path.join(PKG, "libbcf.so")
+OBJDIR = os.path.join(PKG, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["kernels.hip", "api.cpp"]
+SOURCES = ["kernels.hip", "frame_f32.hip", "frame_f16.hip", "frame_bf16.hip", "frame_fp8.hip",
+           "frame_f32_mfma.hip", "calibrate.hip", "api.cpp"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
     # keep the compiler from forming packed fp32 VALU instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # keep MFMA accumulators in VGPRs (no accvgpr copies between layers)
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-I", INCLUDE, "-I", CSRC,
 ]
 
 
-def build(verbose: bool = False) -> str:
-    objs = []
-    for src in SOURCES:
-        obj = os.path.join(CSRC, os.path.splitext(src)[0] + ".o")
-        cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True, stderr=None if verbose else subprocess.DEVNULL)
-        objs.append(obj)
+def _compile(src: str, verbose: bool) -> str:
+    obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
+    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, stderr=subprocess.PIPE, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr}")
+    return obj
+
+
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    from concurrent.futures import ThreadPoolExecutor
+    jobs = jobs or min(len(SOURCES), max(1, min(16, len(os.sched_getaffinity(0)))))
+    os.makedirs(OBJDIR, exist_ok=True)
+    with ThreadPoolExecutor(jobs) as pool:
+        objs = list(pool.map(lambda s: _compile(s, verbose), SOURCES))
     tmp = LIBRARY + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     subprocess.run(cmd, check=True)

@@ -49,6 +49,12 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 uint32_t level_dim(uint32_t d, uint32_t l) { return (d >> l) ? (d >> l) : 1u; }
 
+// texels per row of a level in the texel scratch (the kernels' row_pitch)
+uint32_t scratch_pitch(uint32_t w) { return w + 2u; }
+
+// the texel scratch must stay addressable with 32-bit byte offsets
+constexpr size_t kMaxScratchTexels = ((size_t)1 << 31) / 8;
+
 size_t chain_blocks(uint32_t w, uint32_t h, uint32_t levels, uint32_t *per_level_offset)
 {
     size_t total = 0;
@@ -65,6 +71,7 @@ bool kind_of(bcf_precision p, bcf::MlpKind *k)
     case BCF_FP32: *k = bcf::MLP_VALU_F32; return true;
     case BCF_FP16: *k = bcf::MLP_MFMA_F16; return true;
     case BCF_BF16: *k = bcf::MLP_MFMA_BF16; return true;
+    case BCF_FP8: *k = bcf::MLP_MFMA_FP8; return true;
     case BCF_FP32_MFMA: *k = bcf::MLP_MFMA_F32; return true;
     default: return false;
     }
@@ -102,9 +109,11 @@ bcf_status describe(const bcf_material *m, bcf::MaterialDesc *d, bcf::MlpShape *
         chain_blocks(x.width, x.height, x.levels, T.blk_off);
         for (uint32_t l = 0; l < x.levels; ++l) {
             T.tex_off[l] = (uint32_t)texel_off;
-            texel_off = align_up(texel_off + (size_t)level_dim(x.width, l) * level_dim(x.height, l), 4);
+            texel_off = align_up(texel_off + (size_t)scratch_pitch(level_dim(x.width, l)) * level_dim(x.height, l), 4);
         }
-        if (texel_off > 0xFFFFFFFFull) return fail(BCF_ERR_UNSUPPORTED, "material too large");
+        if (texel_off > kMaxScratchTexels)
+            return fail(BCF_ERR_UNSUPPORTED, "material too large: %zu decoded texels, limit %zu",
+                        texel_off, kMaxScratchTexels);
     }
     if (m->n_layers < 2 || m->n_layers > 4)
         return fail(BCF_ERR_UNSUPPORTED, "n_layers = %u, supported 2..4 (1..3 hidden layers)", m->n_layers);
@@ -135,7 +144,7 @@ size_t scratch_texels(const bcf::MaterialDesc &d)
 {
     const bcf::TexDesc &T = d.tex[d.n_tex - 1];
     const uint32_t l = T.levels - 1;
-    return align_up(T.tex_off[l] + (size_t)level_dim(T.w, l) * level_dim(T.h, l), 4);
+    return align_up(T.tex_off[l] + (size_t)scratch_pitch(level_dim(T.w, l)) * level_dim(T.h, l), 4);
 }
 
 size_t elem_bytes(bcf::MlpKind k)
@@ -143,35 +152,29 @@ size_t elem_bytes(bcf::MlpKind k)
     return (k == bcf::MLP_MFMA_F16 || k == bcf::MLP_MFMA_BF16) ? 2 : k == bcf::MLP_MFMA_FP8 ? 1 : 4;
 }
 
-// Mirrors the operand layouts of the kernels.
+// Workspace: a 256-byte header, the texel scratch (at the same offset for
+// every precision, so bcf_unpack needs none), then each layer's operands and
+// fp32 bias, and the scales.
 bcf::WsLayout layout(const bcf::MaterialDesc &d, const bcf::MlpShape &sh, bcf::MlpKind k)
 {
     bcf::WsLayout lay;
     std::memset(&lay, 0, sizeof lay);
     size_t off = 256;
+    lay.scratch_off = off;
+    lay.scratch_bytes = scratch_texels(d) * 8;
+    off = align_up(off + lay.scratch_bytes, 256);
     lay.weights_off = off;
     const uint32_t L = sh.n_hidden + 1;
     for (uint32_t l = 0; l < L; ++l) {
-        const uint32_t rows = l < sh.n_hidden ? sh.hidden : (k == bcf::MLP_VALU_F32 ? (sh.out <= 10 ? 10u : 16u) : 16u);
-        size_t elems;
-        if (k == bcf::MLP_VALU_F32) {
-            elems = (size_t)rows * (l == 0 ? 12u : sh.hidden);
-        } else {
-            const uint32_t P = k == bcf::MLP_MFMA_F32 ? 1u : 4u;
-            const uint32_t kc = k == bcf::MLP_MFMA_F32 ? (l == 0 ? 3u : sh.hidden / 4) : (l == 0 ? 1u : sh.hidden / 16);
-            elems = (size_t)(rows / 16) * kc * 64 * P;
-        }
         lay.layer_w_off[l] = off;
-        off = align_up(off + elems * elem_bytes(k), 256);
+        off = align_up(off + bcf::mlp_layer_elems(sh, l, k) * elem_bytes(k), 256);
         lay.layer_b_off[l] = off;
-        off = align_up(off + (size_t)rows * 4, 256);
+        off = align_up(off + (size_t)bcf::mlp_layer_rows(sh, l, k) * 4, 256);
     }
     lay.scales_off = off;
-    off = align_up(off + 64, 256);
+    off = align_up(off + 32 * sizeof(float), 256);
     lay.weights_bytes = off - lay.weights_off;
-    lay.scratch_off = off;
-    lay.scratch_bytes = scratch_texels(d) * 8;
-    lay.total = align_up(off + lay.scratch_bytes, 256);
+    lay.total = off;
     return lay;
 }
 
@@ -192,6 +195,32 @@ bcf::PredecodePlan predecode_plan(const bcf::MaterialDesc &d)
     p.seg_wg[p.n_seg] = wg;
     return p;
 }
+
+// The checks shared by bcf_decode and bcf_decode_unpacked.
+bcf_status decode_args(const bcf_material *m, bcf_precision p, const void *ws, const float *queries, size_t n,
+                       float *out, bcf::MaterialDesc *d, bcf::MlpShape *sh, bcf::MlpKind *kind)
+{
+    bcf_status st = describe(m, d, sh);
+    if (st != BCF_OK) return st;
+    if (!kind_of(p, kind)) return fail(BCF_ERR_UNSUPPORTED, "precision %d not supported", (int)p);
+    if (n == 0) return BCF_OK;
+    if (!ws || !aligned(ws, 256)) return fail(BCF_ERR_INVALID_ARG, "workspace NULL or not 256-byte aligned");
+    if (!queries || !aligned(queries, 4)) return fail(BCF_ERR_INVALID_ARG, "queries NULL or misaligned");
+    if (!out || !aligned(out, 4)) return fail(BCF_ERR_INVALID_ARG, "out NULL or misaligned");
+    if (n > (size_t)1 << 40) return fail(BCF_ERR_UNSUPPORTED, "n = %zu too large", n);
+    return BCF_OK;
+}
+
+uint2 *scratch_of(void *ws, const bcf::WsLayout &lay)
+{
+    return reinterpret_cast<uint2 *>(static_cast<uint8_t *>(ws) + lay.scratch_off);
+}
+
+bcf_status unpack(const bcf::MaterialDesc &d, const bcf::WsLayout &lay, void *ws, hipStream_t s)
+{
+    return device_status(bcf::launch_predecode(d, predecode_plan(d), scratch_of(ws, lay), s), "unpack launch");
+}
+
 
 }  // namespace
 
@@ -225,32 +254,74 @@ bcf_status bcf_prepare(const bcf_material *m, bcf_precision p, void *ws, size_t 
     if (*ws_bytes < lay.total)
         return fail(BCF_ERR_INVALID_ARG, "workspace of %zu bytes, need %zu", *ws_bytes, lay.total);
     if (!aligned(ws, 256)) return fail(BCF_ERR_INVALID_ARG, "workspace not 256-byte aligned");
-    return device_status(bcf::launch_prepare_weights(m->params, sh, kind, lay, ws,
+    if (kind == bcf::MLP_MFMA_FP8 && !m->act_absmax)
+        return fail(BCF_ERR_INVALID_ARG, "BCF_FP8 needs act_absmax (see bcf_calibrate)");
+    if (m->act_absmax && !aligned(m->act_absmax, 4))
+        return fail(BCF_ERR_INVALID_ARG, "act_absmax not 4-byte aligned");
+    return device_status(bcf::launch_prepare_weights(m->params, m->act_absmax, sh, kind, lay, ws,
                                                      static_cast<hipStream_t>(stream)),
                          "prepare launch");
 }
 
-bcf_status bcf_decode(const bcf_material *m, bcf_precision p, const void *ws, const float *queries,
-                      size_t n, uint32_t grid_width, float *out, void *stream)
+
+bcf_status bcf_decode(const bcf_material *m, bcf_precision p, void *ws, const float *queries, size_t n,
+                      uint32_t grid_width, float *out, void *stream)
+{
+    bcf::MaterialDesc d;
+    bcf::MlpShape sh;
+    bcf::MlpKind kind;
+    (void)grid_width;
+    bcf_status st = decode_args(m, p, ws, queries, n, out, &d, &sh, &kind);
+    if (st != BCF_OK || n == 0) return st;
+    const bcf::WsLayout lay = layout(d, sh, kind);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    st = unpack(d, lay, ws, s);
+    if (st != BCF_OK) return st;
+    return device_status(bcf::launch_filter_mlp(d, sh, kind, lay, ws, queries, n, out, s), "decode launch");
+}
+
+bcf_status bcf_unpack(const bcf_material *m, void *ws, void *stream)
 {
     bcf::MaterialDesc d;
     bcf::MlpShape sh;
     bcf_status st = describe(m, &d, &sh);
     if (st != BCF_OK) return st;
-    bcf::MlpKind kind;
-    if (!kind_of(p, &kind)) return fail(BCF_ERR_UNSUPPORTED, "precision %d not supported", (int)p);
-    (void)grid_width;
-    if (n == 0) return BCF_OK;
     if (!ws || !aligned(ws, 256)) return fail(BCF_ERR_INVALID_ARG, "workspace NULL or not 256-byte aligned");
-    if (!queries || !aligned(queries, 4)) return fail(BCF_ERR_INVALID_ARG, "queries NULL or misaligned");
-    if (!out || !aligned(out, 4)) return fail(BCF_ERR_INVALID_ARG, "out NULL or misaligned");
-    if (n > (size_t)1 << 40) return fail(BCF_ERR_UNSUPPORTED, "n = %zu too large", n);
+    // the scratch sits at the same offset in every precision's layout
+    const bcf::WsLayout lay = layout(d, sh, bcf::MLP_VALU_F32);
+    return unpack(d, lay, ws, static_cast<hipStream_t>(stream));
+}
+
+bcf_status bcf_decode_unpacked(const bcf_material *m, bcf_precision p, const void *ws, const float *queries,
+                               size_t n, uint32_t grid_width, float *out, void *stream)
+{
+    bcf::MaterialDesc d;
+    bcf::MlpShape sh;
+    bcf::MlpKind kind;
+    (void)grid_width;
+    bcf_status st = decode_args(m, p, ws, queries, n, out, &d, &sh, &kind);
+    if (st != BCF_OK || n == 0) return st;
     const bcf::WsLayout lay = layout(d, sh, kind);
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    uint2 *texels = reinterpret_cast<uint2 *>(static_cast<uint8_t *>(const_cast<void *>(ws)) + lay.scratch_off);
-    st = device_status(bcf::launch_predecode(d, predecode_plan(d), texels, s), "predecode launch");
+    return device_status(bcf::launch_filter_mlp(d, sh, kind, lay, ws, queries, n, out, static_cast<hipStream_t>(stream)),
+                         "decode launch");
+}
+
+bcf_status bcf_calibrate(const bcf_material *m, void *ws, const float *queries, size_t n,
+                         float *act_absmax, void *stream)
+{
+    bcf::MaterialDesc d;
+    bcf::MlpShape sh;
+    bcf_status st = describe(m, &d, &sh);
     if (st != BCF_OK) return st;
-    return device_status(bcf::launch_filter_mlp(d, sh, kind, lay, ws, queries, n, out, s), "decode launch");
+    if (!ws || !aligned(ws, 256)) return fail(BCF_ERR_INVALID_ARG, "workspace NULL or not 256-byte aligned");
+    if (!act_absmax || !aligned(act_absmax, 4)) return fail(BCF_ERR_INVALID_ARG, "act_absmax NULL or misaligned");
+    if (n > 0 && (!queries || !aligned(queries, 4)))
+        return fail(BCF_ERR_INVALID_ARG, "queries NULL or misaligned");
+    const bcf::WsLayout lay = layout(d, sh, bcf::MLP_VALU_F32);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    st = unpack(d, lay, ws, s);
+    if (st != BCF_OK) return st;
+    return device_status(bcf::launch_calibrate(d, sh, lay, ws, queries, n, act_absmax, s), "calibrate launch");
 }
 
 bcf_status bcf_decode_blocks(const void *blocks, size_t n_blocks, uint32_t is_signed, uint16_t *halves,

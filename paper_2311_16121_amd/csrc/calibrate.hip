@@ -1,0 +1,29 @@
+// The fp8 calibration kernel: the plain fp32 decode recording each layer's
+// largest input magnitude.
+#include "frame_kernels.hpp"
+
+namespace bcf {
+
+template <int C, bool SH>
+static hipError_t launch_calib_c(const FrameArgs &a, const MlpShape &sh, unsigned grid, hipStream_t s)
+{
+#define BCF_CASE(H, NH)                                                                       \
+    if (sh.hidden == H && sh.n_hidden == NH) {                                               \
+        k_calibrate<H, NH, C, SH><<<grid, kFrameThreads, 0, s>>>(a);                          \
+        return hipGetLastError();                                                             \
+    }
+    BCF_CASE(16, 1) BCF_CASE(16, 2) BCF_CASE(16, 3)
+    BCF_CASE(32, 1) BCF_CASE(32, 2) BCF_CASE(32, 3)
+    BCF_CASE(64, 1) BCF_CASE(64, 2) BCF_CASE(64, 3)
+#undef BCF_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_calibrate_kernel(const FrameArgs &a, const MlpShape &sh, bool shared, unsigned grid,
+                                   hipStream_t s)
+{
+    if (sh.out <= 10) return shared ? launch_calib_c<10, true>(a, sh, grid, s) : launch_calib_c<10, false>(a, sh, grid, s);
+    return shared ? launch_calib_c<16, true>(a, sh, grid, s) : launch_calib_c<16, false>(a, sh, grid, s);
+}
+
+}  // namespace bcf

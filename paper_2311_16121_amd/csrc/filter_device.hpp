@@ -1,0 +1,145 @@
+// Trilinear filtering of the feature pyramids from the texel scratch
+// (eq. 9 at s_i = s + b_i of eq. 10), for the decode kernels.
+//
+// Texel scratch: level l of pyramid t is max(h>>l,1) rows of pitch w_l + 2
+// texels of 8 bytes (r | g << 16, b as half bit patterns). Column w_l repeats
+// texel 0 of its row, so the two horizontal taps of a bilinear footprint are
+// one 16-byte load, also across the wrap.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "internal.hpp"
+
+namespace bcf {
+
+__host__ __device__ inline uint32_t row_pitch(uint32_t w) { return w + 2u; }
+
+// Per pyramid slot and level, as the kernels read it from LDS:
+//   x = float(w_l), y = float(h_l), z = (w_l - 1) | (h_l - 1) << 16, w = first texel
+struct LevelLut {
+    uint4 e[kMaxTextures][kMaxLevels];
+};
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, uint32_t bytes)
+{
+    // raw buffer: 32-bit byte offsets; loads past `bytes` return 0, stores are dropped
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+__device__ __forceinline__ float half_lo(uint32_t v)
+{
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)(v & 0xFFFFu));
+}
+
+__device__ __forceinline__ float half_hi(uint32_t v)
+{
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)(v >> 16));
+}
+
+struct LevelSel {
+    uint32_t l0, l1;
+    float lam;
+};
+
+__device__ __forceinline__ LevelSel select_levels(float s, float bias, uint32_t levels)
+{
+    // s_i = s + b_i clamped to [0, L-1]; fmaxf maps NaN to 0
+    const float si = fminf(fmaxf(s + bias, 0.0f), (float)(levels - 1));
+    const float lf = floorf(si);
+    LevelSel r;
+    r.l0 = (uint32_t)lf;
+    r.l1 = min(r.l0 + 1, levels - 1);
+    r.lam = si - lf;
+    return r;
+}
+
+// One level's bilinear footprint: byte offsets of the texel pairs
+// (x0, y0)+(x0+1, y0) and (x0, y1)+(x0+1, y1), and the four weights scaled
+// by the level's trilinear weight lw.
+struct Footprint {
+    uint32_t o0, o1;
+    float w00, w10, w01, w11;
+};
+
+__device__ __forceinline__ Footprint footprint(uint4 e, float uf, float vf, float lw)
+{
+    // copy the fields to plain integers before reinterpreting them
+    const uint32_t ew = e.x, eh = e.y, masks = e.z, first = e.w;
+    const float x = fmaf(uf, __builtin_bit_cast(float, ew), -0.5f);
+    const float y = fmaf(vf, __builtin_bit_cast(float, eh), -0.5f);
+    const float fx = __builtin_amdgcn_fractf(x), fy = __builtin_amdgcn_fractf(y);
+    const uint32_t wm = masks & 0xFFFFu, hm = masks >> 16;
+    const uint32_t x0 = (uint32_t)(int)floorf(x) & wm;          // -1 wraps to w-1
+    const uint32_t y0 = (uint32_t)(int)floorf(y) & hm;
+    const uint32_t y1 = (y0 + 1u) & hm;
+    const uint32_t lw2 = __builtin_popcount(wm);                // log2 w
+    // row y starts at y * (w + 2) = (y << log2 w) + 2 y
+    Footprint f;
+    f.o0 = ((y0 << lw2) + 2u * y0 + x0 + first) * 8u;
+    f.o1 = ((y1 << lw2) + 2u * y1 + x0 + first) * 8u;
+    const float wx1 = fx * lw, wx0 = lw - wx1;
+    f.w01 = wx0 * fy;
+    f.w11 = wx1 * fy;
+    f.w00 = wx0 - f.w01;
+    f.w10 = wx1 - f.w11;
+    return f;
+}
+
+// acc[0..2] += the footprint's weighted texels, the level starting `shift`
+// bytes after the footprint's own base
+__device__ __forceinline__ void gather(__amdgpu_buffer_rsrc_t rs, const Footprint &f, uint32_t shift,
+                                      float *acc)
+{
+    const auto r0 = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(f.o0 + shift), 0, 0);
+    const auto r1 = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(f.o1 + shift), 0, 0);
+    acc[0] = fmaf(f.w00, half_lo(r0[0]), acc[0]);
+    acc[0] = fmaf(f.w10, half_lo(r0[2]), acc[0]);
+    acc[0] = fmaf(f.w01, half_lo(r1[0]), acc[0]);
+    acc[0] = fmaf(f.w11, half_lo(r1[2]), acc[0]);
+    acc[1] = fmaf(f.w00, half_hi(r0[0]), acc[1]);
+    acc[1] = fmaf(f.w10, half_hi(r0[2]), acc[1]);
+    acc[1] = fmaf(f.w01, half_hi(r1[0]), acc[1]);
+    acc[1] = fmaf(f.w11, half_hi(r1[2]), acc[1]);
+    acc[2] = fmaf(f.w00, half_lo(r0[1]), acc[2]);
+    acc[2] = fmaf(f.w10, half_lo(r0[3]), acc[2]);
+    acc[2] = fmaf(f.w01, half_lo(r1[1]), acc[2]);
+    acc[2] = fmaf(f.w11, half_lo(r1[3]), acc[2]);
+}
+
+// z[3t + c] = T_t(u, v, s) channel c for the four pyramid slots (slots past
+// the material's pyramids repeat slot 0; their MLP weights are zero).
+// SHARED: every slot has the same w, h, levels and bias and slot t starts
+// t * stride bytes after slot 0, so one footprint serves all four.
+template <bool SHARED>
+__device__ __forceinline__ void filter4(__amdgpu_buffer_rsrc_t rs, const LevelLut &lut,
+                                        const float *levels_bias, uint32_t stride, float u, float v,
+                                        float s, float z[12])
+{
+    const float uf = u - floorf(u), vf = v - floorf(v);       // wrap addressing
+#pragma unroll
+    for (int i = 0; i < 12; ++i) z[i] = 0.0f;
+    if (SHARED) {
+        const LevelSel ls = select_levels(s, levels_bias[1], __builtin_bit_cast(uint32_t, levels_bias[0]));
+        const Footprint f0 = footprint(lut.e[0][ls.l0], uf, vf, 1.0f - ls.lam);
+        const Footprint f1 = footprint(lut.e[0][ls.l1], uf, vf, ls.lam);
+#pragma unroll
+        for (int t = 0; t < kMaxTextures; ++t) {
+            gather(rs, f0, (uint32_t)t * stride, z + 3 * t);
+            gather(rs, f1, (uint32_t)t * stride, z + 3 * t);
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < kMaxTextures; ++t) {
+            const LevelSel ls = select_levels(s, levels_bias[2 * t + 1],
+                                              __builtin_bit_cast(uint32_t, levels_bias[2 * t]));
+            const Footprint f0 = footprint(lut.e[t][ls.l0], uf, vf, 1.0f - ls.lam);
+            const Footprint f1 = footprint(lut.e[t][ls.l1], uf, vf, ls.lam);
+            gather(rs, f0, 0, z + 3 * t);
+            gather(rs, f1, 0, z + 3 * t);
+        }
+    }
+}
+
+}  // namespace bcf

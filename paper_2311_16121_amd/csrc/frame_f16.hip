@@ -1,0 +1,12 @@
+// Decode kernels with the fp16 MFMA MLP.
+#include "frame_kernels.hpp"
+
+namespace bcf {
+
+hipError_t launch_frame_f16(const FrameArgs &a, const MlpShape &sh, bool shared, unsigned grid, hipStream_t s)
+{
+    return shared ? launch_frame_kind<MLP_MFMA_F16, 16, true>(a, sh, grid, s)
+                  : launch_frame_kind<MLP_MFMA_F16, 16, false>(a, sh, grid, s);
+}
+
+}  // namespace bcf

@@ -1,0 +1,15 @@
+// Plain fp32 decode kernels (vector ALU MLP).
+#include "frame_kernels.hpp"
+
+namespace bcf {
+
+hipError_t launch_frame_f32(const FrameArgs &a, const MlpShape &sh, bool shared, unsigned grid, hipStream_t s)
+{
+    if (shared)
+        return sh.out <= 10 ? launch_frame_kind<MLP_VALU_F32, 10, true>(a, sh, grid, s)
+                            : launch_frame_kind<MLP_VALU_F32, 16, true>(a, sh, grid, s);
+    return sh.out <= 10 ? launch_frame_kind<MLP_VALU_F32, 10, false>(a, sh, grid, s)
+                        : launch_frame_kind<MLP_VALU_F32, 16, false>(a, sh, grid, s);
+}
+
+}  // namespace bcf

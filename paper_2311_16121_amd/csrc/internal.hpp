@@ -11,6 +11,9 @@ constexpr int kMaxTextures = 4;
 constexpr int kMaxLevels = 16;
 constexpr int kMaxHidden = 64;
 constexpr int kMaxOut = 16;
+// queries per kernel launch: queries and outputs stay addressable with 32-bit
+// byte offsets (at most 16 outputs of 4 bytes per query)
+constexpr size_t kMaxQueriesPerLaunch = (size_t)1 << 25;
 
 // One feature pyramid as the kernels see it.
 struct TexDesc {
@@ -64,8 +67,15 @@ struct PredecodePlan {
 hipError_t launch_predecode(const MaterialDesc &m, const PredecodePlan &p, uint2 *texels,
                             hipStream_t s);
 
-hipError_t launch_prepare_weights(const float *params, const MlpShape &sh, MlpKind kind,
-                                  const WsLayout &lay, void *ws, hipStream_t s);
+// operand elements and rows of layer l in the workspace (kernels.hip owns the layout)
+size_t mlp_layer_elems(const MlpShape &s, uint32_t l, MlpKind k);
+uint32_t mlp_layer_rows(const MlpShape &s, uint32_t l, MlpKind k);
+
+hipError_t launch_prepare_weights(const float *params, const float *act_absmax, const MlpShape &sh,
+                                  MlpKind kind, const WsLayout &lay, void *ws, hipStream_t s);
+
+hipError_t launch_calibrate(const MaterialDesc &m, const MlpShape &sh, const WsLayout &lay, const void *ws,
+                            const float *queries, size_t n, float *absmax, hipStream_t s);
 
 hipError_t launch_filter_mlp(const MaterialDesc &m, const MlpShape &sh, MlpKind kind,
                              const WsLayout &lay, const void *ws, const float *queries, size_t n,

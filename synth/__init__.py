@@ -101,12 +101,16 @@ def pack_many(mode: int, fields: dict, indices: np.ndarray) -> np.ndarray:
 
 
 def bounded_blocks(n: int, g: np.random.Generator, modes=ALL_MODES,
-                   fraction: float = 0.48) -> np.ndarray:
+                   fraction: float = 0.48, signed: bool = False) -> np.ndarray:
     """Variant B: every endpoint is drawn below cap = floor(fraction * 2^bits)
     of its mode's precision, so every decoded UF16 texel stays below 1.0 and
     absolute error targets are meaningful. Transformed modes draw each other
     endpoint within the signed delta range of the base endpoint and store the
-    delta; partitions and indices are uniform."""
+    delta; partitions and indices are uniform.
+
+    signed=True draws endpoints in (-cap, cap) with cap = floor(fraction *
+    2^(bits-1)) and stores them as two's complement of the mode's precision,
+    so every decoded SF16 texel lies in (-1, 1)."""
     pick = np.asarray(modes)[g.integers(0, len(modes), size=n)]
     out = np.empty((n, 16), np.uint8)
     for m in modes:
@@ -115,21 +119,23 @@ def bounded_blocks(n: int, g: np.random.Generator, modes=ALL_MODES,
         if k == 0:
             continue
         bits, widths, transformed, subsets = MODE_SHAPE[m]
-        cap = int(np.floor(fraction * (1 << bits)))
+        cap = int(np.floor(fraction * (1 << (bits - 1 if signed else bits))))
+        low = -cap + 1 if signed else 0
+        wrap = (1 << bits) - 1
         fields = {}
         n_ep = 2 * subsets
         for c, ch in enumerate("rgb"):
-            base = g.integers(0, cap, size=k)
-            fields[ch + "w"] = base
+            base = g.integers(low, cap, size=k)
+            fields[ch + "w"] = base & wrap
             for j, name in enumerate("xyz"[: n_ep - 1]):
                 if transformed:
                     half = 1 << (widths[c] - 1)
-                    lo = np.maximum(0, base - half)
+                    lo = np.maximum(low, base - half)
                     hi = np.minimum(cap - 1, base + half - 1)
                     target = lo + (g.random(k) * (hi - lo + 1)).astype(np.int64)
                     fields[ch + name] = (target - base) & ((1 << widths[c]) - 1)
                 else:
-                    fields[ch + name] = g.integers(0, cap, size=k)
+                    fields[ch + name] = g.integers(low, cap, size=k) & wrap
         width = 3 if subsets == 2 else 4
         fields["d"] = g.integers(0, 32, size=k) if subsets == 2 else np.zeros(k, np.int64)
         idx = g.integers(0, 1 << width, size=(k, 16))

@@ -55,7 +55,7 @@ def material(bcf, n_tex=4, res=256, levels=9, dims=(12, 16, 16, 9), blocks=FAKE,
         w, h = (res, res) if isinstance(res, int) else res
         tex[i] = _Texture(blocks, w, h, levels, bias)
     d = (C.c_uint32 * len(dims))(*dims)
-    m = _Material(n_tex, tex, len(dims) - 1, d, params, signed)
+    m = _Material(n_tex, tex, len(dims) - 1, d, params, signed, None)
     m._keep = (tex, d)
     return m
 
@@ -97,9 +97,12 @@ def test_invalid_materials_are_rejected(bcf, kwargs, status, msg):
 
 def test_unsupported_precision_and_null_arguments(bcf):
     m = material(bcf)
-    st, _, err = size_query(bcf, m, 3)
+    assert size_query(bcf, m, 3)[0] == 0              # fp8 size query needs no scales
+    n = C.c_size_t(1 << 40)
+    assert bcf.lib.bcf_prepare(C.byref(m), 3, C.c_void_p(FAKE), C.byref(n), None) == 1
+    assert "act_absmax" in bcf.lib.bcf_last_error().decode()
+    st, _, err = size_query(bcf, m, 99)
     assert st == 2 and "precision" in err
-    assert size_query(bcf, m, 99)[0] == 2
     assert bcf.lib.bcf_prepare(None, 0, None, C.byref(C.c_size_t()), None) == 1
     assert bcf.lib.bcf_prepare(C.byref(m), 0, None, None, None) == 1
     # workspace too small / misaligned
@@ -115,6 +118,18 @@ def test_unsupported_precision_and_null_arguments(bcf):
     assert bcf.lib.bcf_decode(C.byref(m), 0, C.c_void_p(FAKE), C.c_void_p(FAKE), 5, 0, None, None) == 1
     assert bcf.lib.bcf_decode(C.byref(m), 0, C.c_void_p(FAKE), C.c_void_p(FAKE + 2), 5, 0,
                               C.c_void_p(FAKE), None) == 1
+    # the two halves of decode
+    assert bcf.lib.bcf_unpack(C.byref(m), None, None) == 1
+    assert bcf.lib.bcf_unpack(C.byref(m), C.c_void_p(FAKE + 16), None) == 1
+    assert bcf.lib.bcf_unpack(C.byref(material(bcf, levels=0)), C.c_void_p(FAKE), None) == 1
+    assert bcf.lib.bcf_decode_unpacked(C.byref(m), 0, None, None, 0, 0, None, None) == 0
+    assert bcf.lib.bcf_decode_unpacked(C.byref(m), 0, None, C.c_void_p(FAKE), 5, 0, C.c_void_p(FAKE), None) == 1
+    assert bcf.lib.bcf_decode_unpacked(C.byref(m), 99, C.c_void_p(FAKE), C.c_void_p(FAKE), 5, 0,
+                                       C.c_void_p(FAKE), None) == 2
+    # calibrate
+    assert bcf.lib.bcf_calibrate(C.byref(m), None, C.c_void_p(FAKE), 5, C.c_void_p(FAKE), None) == 1
+    assert bcf.lib.bcf_calibrate(C.byref(m), C.c_void_p(FAKE), C.c_void_p(FAKE), 5, None, None) == 1
+    assert bcf.lib.bcf_calibrate(C.byref(m), C.c_void_p(FAKE), None, 5, C.c_void_p(FAKE), None) == 1
     # decode_blocks
     assert bcf.lib.bcf_decode_blocks(None, 0, 0, None, None) == 0
     assert bcf.lib.bcf_decode_blocks(None, 4, 0, C.c_void_p(FAKE), None) == 1

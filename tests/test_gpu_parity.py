@@ -62,7 +62,7 @@ def test_decode_blocks_empty_and_one(bcf):
 # ---------------------------------------------------------------------------
 # whole decode
 
-def make(res, levels, dims, variant, n_tex=4, seed=1, bias=None, modes=synth.ALL_MODES):
+def make(res, levels, dims, variant, n_tex=4, seed=1, bias=None, modes=synth.ALL_MODES, signed=False):
     g = synth.rng(seed)
     if isinstance(res, int):
         res = [res] * n_tex
@@ -71,11 +71,14 @@ def make(res, levels, dims, variant, n_tex=4, seed=1, bias=None, modes=synth.ALL
     texs = []
     for (w, h), L in zip(sizes, lv):
         n = synth.chain_blocks(w, h, L)
-        blk = synth.random_mode_blocks(n, g, modes) if variant == "R" else synth.bounded_blocks(n, g, modes)
+        if variant == "R":
+            blk = synth.random_mode_blocks(n, g, modes)
+        else:
+            blk = synth.bounded_blocks(n, g, modes, signed=signed)
         texs.append(blk.reshape(-1))
     params = synth.mlp_params(dims, synth.rng(seed + 1))
     bias = bias or [0.0] * n_tex
-    host = oracle.Material(texs, sizes, lv, dims, params, bias)
+    host = oracle.Material(texs, sizes, lv, dims, params, bias, signed)
     return texs, sizes, lv, params, bias, host
 
 
@@ -87,8 +90,9 @@ def run_gpu(bcf, texs, sizes, lv, dims, params, bias, q, precision, grid_width=0
     return out.cpu().numpy().astype(np.float64)
 
 
-def check(bcf, texs, sizes, lv, dims, params, bias, host, q, precision, atol, rel=False, grid_width=0):
-    got = run_gpu(bcf, texs, sizes, lv, dims, params, bias, q, precision, grid_width)
+def check(bcf, texs, sizes, lv, dims, params, bias, host, q, precision, atol, rel=False, grid_width=0,
+          signed=False):
+    got = run_gpu(bcf, texs, sizes, lv, dims, params, bias, q, precision, grid_width, signed)
     ref = oracle.decode(host, q)
     err = np.abs(got - ref)
     if rel:
@@ -187,3 +191,93 @@ def test_non_finite_queries_are_memory_safe(bcf):
         ok = np.isfinite(q).all(axis=1) & (np.abs(q[:, :2]) < 1e6).all(axis=1)
         ref = oracle.decode(host, q[ok])
         assert np.abs(got[ok] - ref).max() <= (1e-5 if p == "FP32" else 2e-3)
+
+
+@pytest.mark.parametrize("precision,atol", [("FP32", 1e-5), ("FP16", 2e-3), ("FP32_MFMA", 1e-5)])
+def test_signed_pyramids(bcf, precision, atol):
+    # BC6H_SF16 pyramids with texels in (-1, 1)
+    dims = (12, 32, 32, 10)
+    texs, sizes, lv, params, bias, host = make(128, 8, dims, "B", seed=31, signed=True)
+    q = synth.uniform_queries(20011, synth.rng(7), 8.0)
+    log(f"signed {precision}")
+    check(bcf, texs, sizes, lv, dims, params, bias, host, q, bcf.Precision[precision], atol, signed=True)
+
+
+# ---------------------------------------------------------------------------
+# fp8 (OCP e4m3, per-layer weight scales, static activation scales from a
+# calibration batch)
+
+def test_fp8_tracks_the_oracle(bcf):
+    dims = (12, 32, 32, 10)
+    texs, sizes, lv, params, bias, host = make(128, 8, dims, "B", seed=41)
+    mat = bcf.Material.from_host(texs, sizes, lv, dims, params, bias)
+    calib = synth.uniform_queries(50000, synth.rng(42), 8.0)
+    absmax = bcf.calibrate(mat, dev(calib))
+    torch.cuda.synchronize()
+    a = absmax.cpu().numpy()
+    # the calibration's layer-0 maximum is the largest filtered feature seen
+    feats = oracle.sample(host, calib)
+    assert abs(a[0] - np.abs(feats).max()) <= 1e-5
+    assert (a > 0).all()
+    mat.set_act_absmax(absmax)
+    ws = bcf.prepare(mat, bcf.Precision.FP8)
+    q = synth.uniform_queries(20000, synth.rng(43), 8.0)
+    got = bcf.decode(mat, ws, dev(q), bcf.Precision.FP8).cpu().numpy().astype(np.float64)
+    ref = oracle.decode(host, q)
+    err = np.abs(got - ref)
+    scale = np.abs(ref).max()
+    log(f"fp8: max abs err {err.max():.3e}, mean {err.mean():.3e}, output scale {scale:.3f}")
+    assert np.isfinite(got).all()
+    # e4m3 keeps 3 significand bits: errors of a few percent of the output range
+    assert err.mean() <= 0.02 * scale
+    assert err.max() <= 0.15 * scale
+
+
+# ---------------------------------------------------------------------------
+# the full-frame workload in the launch configuration the benchmark times
+
+def test_full_frame_sampled_outputs(bcf):
+    wl = synth.WORKLOADS["frame4k"]
+    m = synth.workload_material(wl, variant="B")
+    q = synth.workload_queries(wl)
+    host = oracle.Material.from_synth(m)
+    mat = bcf.Material.from_host(m.textures, m.res, m.levels, m.dims, m.params)
+    qd = dev(q)
+    pick = np.sort(synth.rng(77).choice(len(q), size=20000, replace=False))
+    # include the frame's first and last rows and the last query
+    pick = np.unique(np.concatenate([pick, np.arange(64), np.arange(len(q) - 64, len(q))]))
+    ref = oracle.decode(host, q[pick])
+    for p, bar in (("FP32", 1e-5), ("FP16", 2e-3), ("FP32_MFMA", 1e-5), ("BF16", 2e-2)):
+        prec = bcf.Precision[p]
+        ws = bcf.prepare(mat, prec)
+        bcf.unpack(mat, ws)                  # the two calls the benchmark times
+        out = bcf.decode_unpacked(mat, ws, qd, prec, grid_width=3840)
+        got = out[torch.from_numpy(pick).cuda()].cpu().numpy().astype(np.float64)
+        err = np.abs(got - ref).max()
+        log(f"frame4k {p}: max abs err {err:.3e} on {len(pick)} sampled queries")
+        assert err <= bar
+        del ws, out
+
+
+def test_unpack_then_decode_unpacked_equals_decode(bcf):
+    texs, sizes, lv, params, bias, host = make(64, 7, (12, 32, 32, 10), "B", seed=21)
+    q = synth.uniform_queries(5000, 7, synth.rng(22))
+    mat = bcf.Material.from_host(texs, sizes, lv, (12, 32, 32, 10), params, bias)
+    qd = dev(q)
+    for p in ("FP32", "FP16"):
+        prec = bcf.Precision[p]
+        ws = bcf.prepare(mat, prec)
+        whole = bcf.decode(mat, ws, qd, prec).cpu().numpy()
+        ws2 = bcf.prepare(mat, prec)
+        ws2.fill_(0xFF)                      # garbage everywhere, then prepare again
+        ws2.copy_(bcf.prepare(mat, prec))
+        bcf.unpack(mat, ws2)
+        a = bcf.decode_unpacked(mat, ws2, qd, prec).cpu().numpy()
+        b = bcf.decode_unpacked(mat, ws2, qd[:1234], prec).cpu().numpy()   # one unpack, two decodes
+        assert np.array_equal(whole.view(np.uint32), a.view(np.uint32))
+        assert np.array_equal(whole[:1234].view(np.uint32), b.view(np.uint32))
+    # unpack takes no precision: its texels sit where every precision's layout reads them
+    ws16 = bcf.prepare(mat, bcf.Precision.FP16)
+    bcf.unpack(mat, ws16)
+    got = bcf.decode_unpacked(mat, ws16, qd, bcf.Precision.FP16).cpu().numpy().astype(np.float64)
+    assert np.abs(got - oracle.decode(host, q)).max() <= 2e-3

@@ -48,7 +48,7 @@ def run(shim, blocks, signed):
 def test_random_blocks_every_mode(shim, signed):
     g = synth.rng(1000 + signed)
     blocks = np.concatenate([synth.random_mode_blocks(60000, g), synth.reserved_blocks(2000, g),
-                             synth.bounded_blocks(20000, g)])
+                             synth.bounded_blocks(20000, g), synth.bounded_blocks(20000, g, signed=True)])
     got = run(shim, blocks, signed)
     ref = oracle.decode_blocks(blocks, signed)
     bad = np.nonzero((got != ref).any(axis=(1, 2)))[0]

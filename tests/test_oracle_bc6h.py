@@ -215,3 +215,72 @@ def test_packer_round_trip_recovers_fields():
             assert got["mode"] == mode
             for k, v in f.items():
                 assert got[k] == v, (mode, k, v, got[k])
+
+
+# ---------------------------------------------------------------------------
+# signed format (BC6H_SF16)
+
+@pytest.mark.parametrize("mode,bits", [(11, 10), (12, 11), (13, 12), (10, 6)])
+def test_signed_constant_blocks_follow_eq6(mode, bits):
+    # eq. (6) with a = 31/32 for the signed format: a constant block of code e
+    # (two's complement of `bits`) decodes to sign(e) a (2^16 |e| + 2^15) / 2^b
+    # within 1.5 below in magnitude, with the half's sign bit for e < 0. Zero
+    # gives 0; magnitudes at the top code saturate to 31743.
+    half = 1 << (bits - 1)
+    step = max(1, half // 1500)
+    for e in list(range(-half + 1, half, step)) + [half - 1, -(half - 1)]:
+        s = e & ((1 << bits) - 1)
+        fields = {"rw": s, "gw": s, "bw": s}
+        if mode == 11:
+            fields.update(rx=s, gx=s, bx=s)
+        if mode == 10:
+            fields.update(rx=s, gx=s, bx=s, ry=s, gy=s, by=s, rz=s, gz=s, bz=s, d=3)
+        m, out = oracle.decode_block(bc6h_pack.pack(mode, fields, [0] * 16), signed=True)
+        assert m == mode and (out == out[0, 0]).all()
+        y = int(out[0, 0])
+        mag, neg = y & 0x7FFF, bool(y & 0x8000)
+        if e == 0:
+            assert y == 0
+        elif abs(e) >= half - 1:
+            assert mag == 31743 and neg == (e < 0)
+        else:
+            eq6 = 31 / 32 * (2 ** 16 * abs(e) + 2 ** 15) / 2 ** bits
+            assert 0 <= eq6 - mag < 1.5, (e, y, eq6)
+            assert neg == (e < 0)
+
+
+@pytest.mark.parametrize("mode", range(1, 15))
+def test_signed_negation_symmetry(mode):
+    # Negating every endpoint (the stored base and every stored delta, in two's
+    # complement of their widths) negates every texel; the blend's rounding to
+    # nearest with ties up can shift a magnitude by one unit.
+    g = synth.rng(600 + mode)
+    blocks = synth.bounded_blocks(300, g, modes=(mode,), signed=True)
+    bits, widths, transformed, subsets = bc6h_pack.MODE_SHAPE[mode]
+    checked = 0
+    for blk in blocks:
+        f = oracle.block_fields(blk.tobytes())
+        # the most negative stored delta has no positive counterpart
+        if transformed and any(f[ch + name] == 1 << (widths[i] - 1)
+                               for i, ch in enumerate("rgb") for name in "xyz"[: 2 * subsets - 1]):
+            continue
+        checked += 1
+        neg = {}
+        for ch_i, ch in enumerate("rgb"):
+            neg[ch + "w"] = (-f[ch + "w"]) & ((1 << bits) - 1)
+            for name in "xyz"[: 2 * subsets - 1]:
+                w = widths[ch_i] if transformed else bits
+                neg[ch + name] = (-f[ch + name]) & ((1 << w) - 1)
+        neg["d"] = f["d"]
+        bits_in = int.from_bytes(blk.tobytes(), "little")
+        header = bc6h_pack.header_bits(mode)
+        idx = bits_in >> header
+        p = int.from_bytes(bc6h_pack.pack(mode, neg, [0] * 16), "little")
+        p |= idx << header
+        a = oracle.decode_block(blk.tobytes(), signed=True)[1].astype(np.int64)
+        b = oracle.decode_block(p.to_bytes(16, "little"), signed=True)[1].astype(np.int64)
+        ma, mb = a & 0x7FFF, b & 0x7FFF
+        assert (np.abs(ma - mb) <= 1).all()
+        nz = (ma > 1) & (mb > 1)
+        assert ((a[nz] & 0x8000) != (b[nz] & 0x8000)).all()
+    assert checked > 100
