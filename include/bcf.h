@@ -157,6 +157,69 @@ bcf_status bcf_calibrate(const bcf_material *m, void *ws, const float *queries, 
 bcf_status bcf_decode_blocks(const void *blocks, size_t n_blocks, uint32_t is_signed,
                              uint16_t *halves, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Training-time decode (Section 4.2, "Trainable BC6 decompression"; the
+ * training of eqs. (4)-(5) differentiates through it).
+ *
+ * A trainable pyramid keeps, per 4x4 block of every level, the continuous
+ * parameters of the two-subset BC6H mode the features are exported in
+ * (Section 5.2: 6-bit endpoints, 3-bit indices) and a fixed partition
+ * (Section 5.1, "Partition selection strategy"):
+ *   endpoints  e_1..e_4 per channel, in quantised units (valid range [0, 63])
+ *   indices    x per texel (valid range [0, 1])
+ *   partition  k in 0..31 (only the low 5 bits are read)
+ * Texel t of a block lies in subset sigma = bit t of partition mask k and
+ * blends the pair (e_{2 sigma + 1}, e_{2 sigma + 2}):
+ *   continuous:        y = a ((2^16 e_A + 2^15) + x 2^16 (e_B - e_A)) / 2^6,
+ *                      a = 31/64 (eqs. (6), (7)), texel = eq. (8) of y;
+ *   straight-through:  texel = the format's exact decode of the block with
+ *                      endpoints rounded to integers in [0, 63] and indices
+ *                      to i = rint(7 x) in [0, 7] -- the exported block;
+ *                      gradients as in the continuous case at the rounded
+ *                      point (x = w_i / 64, w_i the format's 3-bit weight),
+ *                      the rounding passed through as the identity, and
+ *                      eq. (8)'s slope taken at the decoded half.
+ * Filtering and the MLP are those of bcf_decode (eqs. (9), (10), (3)) in
+ * binary32, with every hidden layer of 16 or 32 units.
+ * ------------------------------------------------------------------------ */
+
+typedef struct {
+    uint32_t width, height;        /* powers of two */
+    uint32_t levels;               /* 1 .. log2(max(width, height)) + 1 */
+    float lod_bias;                /* b_i of eq. (10) */
+    const float *endpoints;        /* device [n_blocks][4][3], levels back to back */
+    const float *indices;          /* device [n_blocks][16] */
+    const uint8_t *partitions;     /* device [n_blocks] */
+} bcf_train_texture;
+
+typedef struct {
+    uint32_t n_textures;                  /* 1..4 */
+    const bcf_train_texture *textures;    /* host array [n_textures] */
+    uint32_t n_layers;                    /* 2..4 */
+    const uint32_t *dims;                 /* host [n_layers + 1]; hidden widths 16 or 32 */
+    const float *params;                  /* device, layout as in bcf_material */
+    uint32_t straight_through;            /* 0 continuous, 1 straight-through */
+} bcf_train_material;
+
+/* Device workspace bytes (256-byte aligned start) for the training calls
+ * on this material: two texel images of 16 bytes per texel. */
+bcf_status bcf_train_workspace_size(const bcf_train_material *m, size_t *ws_bytes);
+
+/* G(u, v, s) for n queries (device [n][3]) into out (device [n][dims[n_layers]]),
+ * evaluated from the current parameters. */
+bcf_status bcf_train_forward(const bcf_train_material *m, void *ws, const float *queries, size_t n,
+                             float *out, void *stream);
+
+/* Vector-Jacobian product of bcf_train_forward: given grad_out = dL/dG
+ * (device [n][dims[n_layers]]), overwrites grad_endpoints[i] (device,
+ * texture i's endpoint layout), grad_indices[i] and grad_params (device, the
+ * params layout) with dL/d parameter. grad_endpoints and grad_indices are host
+ * arrays of n_textures device pointers. Sums use float atomics, so results
+ * vary in the last bits from run to run. */
+bcf_status bcf_train_backward(const bcf_train_material *m, void *ws, const float *queries, size_t n,
+                              const float *grad_out, float *const *grad_endpoints,
+                              float *const *grad_indices, float *grad_params, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -57,6 +57,8 @@ def lib():
         L.bcfo_decode_blocks.argtypes = [C.c_void_p, C.c_size_t, C.c_int, C.c_void_p]
         L.bcfo_block_fields.restype = C.c_int
         L.bcfo_block_fields.argtypes = [C.c_void_p, C.c_void_p]
+        L.bcfo_partition.restype = C.c_int
+        L.bcfo_partition.argtypes = [C.c_int, C.POINTER(C.c_uint16), C.POINTER(C.c_int)]
         L.bcfo_mode_bit_budget.restype = C.c_int
         L.bcfo_mode_bit_budget.argtypes = [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.bcfo_texture_bytes.restype = C.c_size_t
@@ -96,6 +98,14 @@ def block_fields(block) -> dict:
     lib().bcfo_block_fields(b.ctypes.data, f.ctypes.data)
     names = ["rw", "gw", "bw", "rx", "gx", "bx", "ry", "gy", "by", "rz", "gz", "bz", "d", "mode"]
     return {k: int(v) for k, v in zip(names, f)}
+
+
+def partition(k: int):
+    """(mask, anchor) of two-subset partition k: mask bit t puts texel t in subset 1."""
+    mask, anchor = C.c_uint16(0), C.c_int(0)
+    if lib().bcfo_partition(k, C.byref(mask), C.byref(anchor)) != 0:
+        raise ValueError(f"partition {k} out of range")
+    return int(mask.value), int(anchor.value)
 
 
 def mode_bit_budget(mode: int):

@@ -284,6 +284,14 @@ int bcfo_block_fields(const uint8_t block[16], int32_t fields[14])
     return mode_number;
 }
 
+int bcfo_partition(int k, uint16_t *mask, int *anchor)
+{
+    if (k < 0 || k > 31) return -1;
+    if (mask) *mask = PARTITION_MASK[k];
+    if (anchor) *anchor = PARTITION_ANCHOR[k];
+    return 0;
+}
+
 int bcfo_mode_bit_budget(int mode, int *header_bits, int *index_bits)
 {
     if (mode < 1 || mode > 14) return -1;

@@ -60,6 +60,10 @@ void bcfo_decode_blocks(const uint8_t *blocks, size_t n, int is_signed, uint16_t
  * then partition, mode. Used by tests that inspect the layout. */
 int bcfo_block_fields(const uint8_t block[16], int32_t fields[14]);
 
+/* Two-subset partition k (0..31): mask bit t set puts texel t in subset 1;
+ * anchor is subset 1's anchor texel. Returns -1 for k out of range. */
+int bcfo_partition(int k, uint16_t *mask, int *anchor);
+
 /* Bit budget of a 1-based mode: endpoint/mode/partition bits and index bits.
  * Returns their sum (128 for every valid mode), or -1 for an invalid mode. */
 int bcfo_mode_bit_budget(int mode, int *header_bits, int *index_bits);

@@ -38,6 +38,18 @@ class _Material(C.Structure):
                 ("params", C.c_void_p), ("is_signed", C.c_uint32), ("act_absmax", C.c_void_p)]
 
 
+class _TrainTexture(C.Structure):
+    _fields_ = [("width", C.c_uint32), ("height", C.c_uint32), ("levels", C.c_uint32),
+                ("lod_bias", C.c_float), ("endpoints", C.c_void_p), ("indices", C.c_void_p),
+                ("partitions", C.c_void_p)]
+
+
+class _TrainMaterial(C.Structure):
+    _fields_ = [("n_textures", C.c_uint32), ("textures", C.POINTER(_TrainTexture)),
+                ("n_layers", C.c_uint32), ("dims", C.POINTER(C.c_uint32)), ("params", C.c_void_p),
+                ("straight_through", C.c_uint32)]
+
+
 def _load():
     if not os.path.exists(LIBRARY):
         raise ImportError(f"{LIBRARY} is not built; run `python paper_2311_16121_amd/build.py`")
@@ -59,6 +71,15 @@ def _load():
     L.bcf_calibrate.restype = C.c_int
     L.bcf_calibrate.argtypes = [C.POINTER(_Material), C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p,
                                 C.c_void_p]
+    L.bcf_train_workspace_size.restype = C.c_int
+    L.bcf_train_workspace_size.argtypes = [C.POINTER(_TrainMaterial), C.POINTER(C.c_size_t)]
+    L.bcf_train_forward.restype = C.c_int
+    L.bcf_train_forward.argtypes = [C.POINTER(_TrainMaterial), C.c_void_p, C.c_void_p, C.c_size_t,
+                                    C.c_void_p, C.c_void_p]
+    L.bcf_train_backward.restype = C.c_int
+    L.bcf_train_backward.argtypes = [C.POINTER(_TrainMaterial), C.c_void_p, C.c_void_p, C.c_size_t,
+                                     C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                     C.c_void_p, C.c_void_p]
     L.bcf_decode_blocks.restype = C.c_int
     L.bcf_decode_blocks.argtypes = [C.c_void_p, C.c_size_t, C.c_uint32, C.c_void_p, C.c_void_p]
     if L.bcf_abi_version() != ABI_VERSION:
@@ -69,7 +90,8 @@ def _load():
 lib = _load()
 
 EXPORTED = ("bcf_abi_version", "bcf_last_error", "bcf_texture_bytes", "bcf_prepare",
-            "bcf_decode", "bcf_unpack", "bcf_decode_unpacked", "bcf_calibrate", "bcf_decode_blocks")
+            "bcf_decode", "bcf_unpack", "bcf_decode_unpacked", "bcf_calibrate", "bcf_decode_blocks",
+            "bcf_train_workspace_size", "bcf_train_forward", "bcf_train_backward")
 
 
 def _check(status: int, what: str):
@@ -235,3 +257,128 @@ def decode_blocks(blocks, signed: bool = False, stream=None):
     _check(lib.bcf_decode_blocks(C.c_void_p(b.data_ptr()), n, int(signed), C.c_void_p(out.data_ptr()),
                                  _stream(stream)), "bcf_decode_blocks")
     return out
+
+
+# ---------------------------------------------------------------------------
+# training-time decode (include/bcf.h, bcf_train_*)
+
+class TrainGeometry:
+    """Everything about a trainable material except its trainable tensors:
+    pyramid sizes and level counts, the fixed partition ids (uint8 device
+    tensors, one per pyramid), MLP dims, LOD biases and the rounding mode."""
+
+    def __init__(self, sizes, levels, partitions, dims, lod_bias=None, straight_through=False):
+        import torch
+        self.sizes = [(s, s) if isinstance(s, int) else tuple(s) for s in sizes]
+        self.levels = list(levels)
+        self.partitions = [p.contiguous() for p in partitions]
+        for p in self.partitions:
+            if p.dtype != torch.uint8 or not p.is_cuda:
+                raise TypeError("partitions must be uint8 device tensors")
+        self.dims = tuple(int(d) for d in dims)
+        self.lod_bias = list(lod_bias) if lod_bias is not None else [0.0] * len(self.sizes)
+        self.straight_through = bool(straight_through)
+
+    def struct(self, endpoints, indices, params):
+        n = len(self.sizes)
+        tex = (_TrainTexture * n)()
+        for i in range(n):
+            w, h = self.sizes[i]
+            tex[i] = _TrainTexture(w, h, self.levels[i], float(self.lod_bias[i]), endpoints[i].data_ptr(),
+                                   indices[i].data_ptr(), self.partitions[i].data_ptr())
+        dims = (C.c_uint32 * len(self.dims))(*self.dims)
+        m = _TrainMaterial(n, tex, len(self.dims) - 1, dims, params.data_ptr(), int(self.straight_through))
+        m._keep = (tex, dims)
+        return m
+
+    def workspace(self, m, device):
+        import torch
+        nbytes = C.c_size_t(0)
+        _check(lib.bcf_train_workspace_size(C.byref(m), C.byref(nbytes)), "bcf_train_workspace_size")
+        ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=device)
+        off = (-ws.data_ptr()) % 256
+        return ws[off: off + nbytes.value]
+
+
+def _check_train_tensors(geo, endpoints, indices, params):
+    import torch
+    for t in list(endpoints) + list(indices) + [params]:
+        if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+            raise TypeError("trainable tensors must be contiguous float32 device tensors")
+    if len(endpoints) != len(geo.sizes) or len(indices) != len(geo.sizes):
+        raise ValueError("one endpoints and one indices tensor per pyramid")
+
+
+def train_forward(geo: TrainGeometry, endpoints, indices, params, queries, stream=None):
+    """G(u, v, s) [n, dims[-1]] from the current trainable tensors (no autograd)."""
+    import torch
+    _check_train_tensors(geo, endpoints, indices, params)
+    q = _queries(queries)
+    m = geo.struct(endpoints, indices, params)
+    ws = geo.workspace(m, q.device)
+    out = torch.empty((q.shape[0], geo.dims[-1]), dtype=torch.float32, device=q.device)
+    _check(lib.bcf_train_forward(C.byref(m), C.c_void_p(ws.data_ptr()), C.c_void_p(q.data_ptr()), q.shape[0],
+                                 C.c_void_p(out.data_ptr()), _stream(stream)), "bcf_train_forward")
+    return out
+
+
+def train_backward(geo: TrainGeometry, endpoints, indices, params, queries, grad_out, stream=None):
+    """(d endpoints list, d indices list, d params) for dL/dG = grad_out."""
+    import torch
+    _check_train_tensors(geo, endpoints, indices, params)
+    q = _queries(queries)
+    go = grad_out.contiguous()
+    if go.dtype != torch.float32 or tuple(go.shape) != (q.shape[0], geo.dims[-1]):
+        raise TypeError("grad_out must be float32 [n, dims[-1]]")
+    m = geo.struct(endpoints, indices, params)
+    ws = geo.workspace(m, q.device)
+    g_end = [torch.empty_like(e) for e in endpoints]
+    g_idx = [torch.empty_like(x) for x in indices]
+    g_par = torch.empty_like(params)
+    n = len(endpoints)
+    ge = (C.c_void_p * n)(*[t.data_ptr() for t in g_end])
+    gi = (C.c_void_p * n)(*[t.data_ptr() for t in g_idx])
+    _check(lib.bcf_train_backward(C.byref(m), C.c_void_p(ws.data_ptr()), C.c_void_p(q.data_ptr()), q.shape[0],
+                                  C.c_void_p(go.data_ptr()), ge, gi, C.c_void_p(g_par.data_ptr()),
+                                  _stream(stream)), "bcf_train_backward")
+    return g_end, g_idx, g_par
+
+
+_TRAIN_FN = None
+
+
+def _train_function():
+    global _TRAIN_FN
+    if _TRAIN_FN is None:
+        import torch
+
+        class TrainDecode(torch.autograd.Function):
+            """G(u, v, s) as a differentiable function of the block parameters
+            and the MLP parameters; backward runs the library's kernels."""
+
+            @staticmethod
+            def forward(ctx, geo, queries, params, *leaves):
+                n = len(geo.sizes)
+                ends, idxs = list(leaves[:n]), list(leaves[n:])
+                ctx.geo = geo
+                ctx.save_for_backward(queries, params, *leaves)
+                return train_forward(geo, ends, idxs, params, queries)
+
+            @staticmethod
+            def backward(ctx, grad_out):
+                geo = ctx.geo
+                queries, params, *leaves = ctx.saved_tensors
+                n = len(geo.sizes)
+                g_end, g_idx, g_par = train_backward(geo, leaves[:n], leaves[n:], params, queries,
+                                                     grad_out.contiguous())
+                return (None, None, g_par, *g_end, *g_idx)
+
+        _TRAIN_FN = TrainDecode
+    return _TRAIN_FN
+
+
+def train_decode(geo: TrainGeometry, endpoints, indices, params, queries):
+    """Differentiable training-time decode: a torch.autograd.Function whose
+    backward is bcf_train_backward (gradients for endpoints, indices and
+    params; none for the queries)."""
+    return _train_function().apply(geo, queries, params, *endpoints, *indices)

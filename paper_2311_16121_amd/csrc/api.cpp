@@ -12,6 +12,7 @@
 #include <string>
 
 #include "internal.hpp"
+#include "train.hpp"
 
 namespace {
 
@@ -222,6 +223,89 @@ bcf_status unpack(const bcf::MaterialDesc &d, const bcf::WsLayout &lay, void *ws
 }
 
 
+// Validates a trainable material and fills the kernels' descriptor (without
+// workspace or gradient pointers). *ws_bytes receives the workspace size.
+bcf_status describe_train(const bcf_train_material *m, bcf::TrainDesc *d, size_t *ws_bytes)
+{
+    if (!m) return fail(BCF_ERR_INVALID_ARG, "material is NULL");
+    if (m->n_textures < 1 || m->n_textures > (uint32_t)bcf::kMaxTextures)
+        return fail(BCF_ERR_INVALID_ARG, "n_textures = %u, expected 1..%d", m->n_textures, bcf::kMaxTextures);
+    if (!m->textures) return fail(BCF_ERR_INVALID_ARG, "textures is NULL");
+    if (m->straight_through > 1) return fail(BCF_ERR_INVALID_ARG, "straight_through = %u, expected 0 or 1",
+                                             m->straight_through);
+    std::memset(d, 0, sizeof *d);
+    d->n_tex = m->n_textures;
+    d->ste = m->straight_through;
+    size_t texels = 0, blocks = 0;
+    for (uint32_t t = 0; t < m->n_textures; ++t) {
+        const bcf_train_texture &x = m->textures[t];
+        if (!is_pow2(x.width) || !is_pow2(x.height) || x.width > 32768 || x.height > 32768)
+            return fail(BCF_ERR_INVALID_ARG, "texture %u: %ux%u is not a power-of-two size <= 32768", t, x.width,
+                        x.height);
+        if (x.levels < 1 || x.levels > log2u(x.width > x.height ? x.width : x.height) + 1)
+            return fail(BCF_ERR_INVALID_ARG, "texture %u: levels = %u out of range", t, x.levels);
+        if (!std::isfinite(x.lod_bias)) return fail(BCF_ERR_INVALID_ARG, "texture %u: lod_bias not finite", t);
+        if (!x.endpoints || !aligned(x.endpoints, 4) || !x.indices || !aligned(x.indices, 4) || !x.partitions)
+            return fail(BCF_ERR_INVALID_ARG, "texture %u: endpoints, indices or partitions NULL or misaligned", t);
+        bcf::TrainTexDesc &td = d->tex[t];
+        td.endpoints = x.endpoints;
+        td.indices = x.indices;
+        td.partitions = x.partitions;
+        td.w = x.width;
+        td.h = x.height;
+        td.levels = x.levels;
+        td.bias = x.lod_bias;
+        td.n_blocks = (uint32_t)chain_blocks(x.width, x.height, x.levels, td.blk_off);
+        d->blk_base[t] = (uint32_t)blocks;
+        blocks += td.n_blocks;
+        for (uint32_t l = 0; l < x.levels; ++l) {
+            td.tex_off[l] = (uint32_t)texels;
+            texels += (size_t)level_dim(x.width, l) * level_dim(x.height, l);
+        }
+    }
+    d->blk_base[m->n_textures] = (uint32_t)blocks;
+    if (texels > ((size_t)1 << 27)) return fail(BCF_ERR_UNSUPPORTED, "%zu texels, at most 2^27", texels);
+    d->n_texels = (uint32_t)texels;
+    if (m->n_layers < 2 || m->n_layers > 4)
+        return fail(BCF_ERR_UNSUPPORTED, "n_layers = %u, expected 2..4", m->n_layers);
+    if (!m->dims) return fail(BCF_ERR_INVALID_ARG, "dims is NULL");
+    if (m->dims[0] != 3 * m->n_textures)
+        return fail(BCF_ERR_INVALID_ARG, "dims[0] = %u, expected 3 * n_textures = %u", m->dims[0], 3 * m->n_textures);
+    const uint32_t hidden = m->dims[1];
+    for (uint32_t l = 1; l < m->n_layers; ++l)
+        if (m->dims[l] != hidden || (hidden != 16 && hidden != 32))
+            return fail(BCF_ERR_UNSUPPORTED, "hidden widths must all be 16 or 32 for training (dims[%u] = %u)", l,
+                        m->dims[l]);
+    const uint32_t out = m->dims[m->n_layers];
+    if (out < 1 || out > (uint32_t)bcf::kMaxOut)
+        return fail(BCF_ERR_UNSUPPORTED, "output width %u, expected 1..%d", out, bcf::kMaxOut);
+    if (!m->params || !aligned(m->params, 4)) return fail(BCF_ERR_INVALID_ARG, "params NULL or misaligned");
+    d->params = m->params;
+    d->n_layers = m->n_layers;
+    uint32_t off = 0;
+    for (uint32_t l = 0; l < m->n_layers; ++l) {
+        d->dims[l] = m->dims[l];
+        d->w_off[l] = off;
+        off += m->dims[l] * m->dims[l + 1];
+        d->b_off[l] = off;
+        off += m->dims[l + 1];
+    }
+    d->dims[m->n_layers] = out;
+    d->n_params = off;
+    *ws_bytes = 2 * align_up(texels * 16, 256);
+    return BCF_OK;
+}
+
+bcf_status bind_train_ws(bcf::TrainDesc *d, void *ws, size_t ws_bytes)
+{
+    if (!ws || !aligned(ws, 256)) return fail(BCF_ERR_INVALID_ARG, "workspace NULL or not 256-byte aligned");
+    (void)ws_bytes;
+    uint8_t *p = static_cast<uint8_t *>(ws);
+    d->texels = reinterpret_cast<float4 *>(p);
+    d->g_texels = reinterpret_cast<float4 *>(p + align_up((size_t)d->n_texels * 16, 256));
+    return BCF_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -334,6 +418,54 @@ bcf_status bcf_decode_blocks(const void *blocks, size_t n_blocks, uint32_t is_si
     return device_status(bcf::launch_decode_blocks(static_cast<const uint4 *>(blocks), n_blocks, is_signed,
                                                    halves, static_cast<hipStream_t>(stream)),
                          "decode_blocks launch");
+}
+
+bcf_status bcf_train_workspace_size(const bcf_train_material *m, size_t *ws_bytes)
+{
+    if (!ws_bytes) return fail(BCF_ERR_INVALID_ARG, "ws_bytes is NULL");
+    bcf::TrainDesc d;
+    return describe_train(m, &d, ws_bytes);
+}
+
+bcf_status bcf_train_forward(const bcf_train_material *m, void *ws, const float *queries, size_t n, float *out,
+                             void *stream)
+{
+    bcf::TrainDesc d;
+    size_t need;
+    bcf_status st = describe_train(m, &d, &need);
+    if (st != BCF_OK) return st;
+    if (n == 0) return BCF_OK;
+    if ((st = bind_train_ws(&d, ws, need)) != BCF_OK) return st;
+    if (!queries || !aligned(queries, 4)) return fail(BCF_ERR_INVALID_ARG, "queries NULL or misaligned");
+    if (!out || !aligned(out, 4)) return fail(BCF_ERR_INVALID_ARG, "out NULL or misaligned");
+    if (n > bcf::kMaxQueriesPerLaunch) return fail(BCF_ERR_UNSUPPORTED, "n = %zu, at most 2^25", n);
+    return device_status(bcf::launch_train_forward(d, queries, n, out, static_cast<hipStream_t>(stream)),
+                         "train forward launch");
+}
+
+bcf_status bcf_train_backward(const bcf_train_material *m, void *ws, const float *queries, size_t n,
+                              const float *grad_out, float *const *grad_endpoints, float *const *grad_indices,
+                              float *grad_params, void *stream)
+{
+    bcf::TrainDesc d;
+    size_t need;
+    bcf_status st = describe_train(m, &d, &need);
+    if (st != BCF_OK) return st;
+    if ((st = bind_train_ws(&d, ws, need)) != BCF_OK) return st;
+    if (n > 0 && (!queries || !aligned(queries, 4) || !grad_out || !aligned(grad_out, 4)))
+        return fail(BCF_ERR_INVALID_ARG, "queries or grad_out NULL or misaligned");
+    if (n > bcf::kMaxQueriesPerLaunch) return fail(BCF_ERR_UNSUPPORTED, "n = %zu, at most 2^25", n);
+    if (!grad_endpoints || !grad_indices) return fail(BCF_ERR_INVALID_ARG, "gradient pointer arrays NULL");
+    if (!grad_params || !aligned(grad_params, 4)) return fail(BCF_ERR_INVALID_ARG, "grad_params NULL or misaligned");
+    for (uint32_t t = 0; t < d.n_tex; ++t) {
+        if (!grad_endpoints[t] || !aligned(grad_endpoints[t], 4) || !grad_indices[t] || !aligned(grad_indices[t], 4))
+            return fail(BCF_ERR_INVALID_ARG, "texture %u: gradient buffers NULL or misaligned", t);
+        d.tex[t].g_endpoints = grad_endpoints[t];
+        d.tex[t].g_indices = grad_indices[t];
+    }
+    d.g_params = grad_params;
+    return device_status(bcf::launch_train_backward(d, queries, n, grad_out, static_cast<hipStream_t>(stream)),
+                         "train backward launch");
 }
 
 }  // extern "C"

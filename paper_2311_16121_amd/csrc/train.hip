@@ -1,0 +1,541 @@
+// Training-time decode for gfx950: forward and backward through the simulated
+// BC6H decompression of Section 4.2 (eqs. 6-8), the trilinear filter (eqs. 9
+// and 10) and the ReLU MLP (eq. 3).
+//
+//   k_train_texels    block parameters -> texel images (r, g, b, 0) per level
+//   k_train_forward   queries -> G(u, v, s), one lane per query
+//   k_train_backward  queries, dL/dG -> dL/d texel (float atomics) and
+//                     dL/d MLP parameters (per-wave sums through LDS)
+//   k_train_blocks    dL/d texel -> dL/d endpoints, dL/d indices (one lane
+//                     per texel, sums over a block's 16 lanes by shuffles)
+//
+// A texel of subset sigma blends the endpoint pair (e_{2 sigma}, e_{2 sigma+1})
+// with index x. Continuous mode: y = a ((2^16 e_A + 2^15)/2^6 + x (2^16 (e_B -
+// e_A))/2^6), w = eq. (8) of y. Straight-through mode: w is the format's exact
+// decode of the rounded endpoints and index (i = rint(7 x)); the derivatives are
+// those of the continuous chain at the rounded point (x = w_i / 64), with the
+// rounding taken as the identity and eq. (8)'s slope at the decoded bits.
+#include <hip/hip_runtime.h>
+
+#include "bc6h_device.hpp"
+#include "train.hpp"
+
+namespace bcf {
+namespace {
+
+constexpr float kA = 31.0f / 64.0f;      // a of eq. (6) for the unsigned format
+constexpr int kTrainThreads = 256;
+constexpr int kTrainWaves = kTrainThreads / 64;
+
+__global__ void __launch_bounds__(256) k_train_zero(float *p, uint32_t n)
+{
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0.0f;
+}
+
+__device__ __forceinline__ void wave_sync_lds()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ---------------------------------------------------------------------------
+// one texel channel
+
+struct TexelChan {
+    float w;              // texel value
+    float slope;          // dw/dy of eq. (8)
+    float dy_da, dy_db;   // dy/d e_A, dy/d e_B
+    float dy_dx;          // dy/d x
+};
+
+// h(y) = max(floor((y - 1) / 1024) - 1, 0) of eq. (8) for integer y >= 0
+__device__ __forceinline__ int h_of_bits(uint32_t y)
+{
+    const int k = y ? (int)((y - 1u) >> 10) - 1 : 0;
+    return k > 0 ? k : 0;
+}
+
+template <bool STE>
+__device__ __forceinline__ TexelChan texel_chan(float ea, float eb, float x)
+{
+    TexelChan r;
+    if (!STE) {
+        // (2^16 e + 2^15) / 2^6 = 1024 e + 512, exact in binary32 for e in [0, 64)
+        const float abar = fmaf(1024.0f, ea, 512.0f);
+        const float bbar = fmaf(1024.0f, eb, 512.0f);
+        const float y = kA * fmaf(x, bbar - abar, abar);
+        const float h = fmaxf(floorf((y - 1.0f) * (1.0f / 1024.0f)) - 1.0f, 0.0f);
+        r.w = ldexpf(y * (1.0f / 1024.0f) - h, (int)h - 14);
+        r.slope = ldexpf(1.0f, (int)h - 24);
+        r.dy_da = kA * 1024.0f * (1.0f - x);
+        r.dy_db = kA * 1024.0f * x;
+        r.dy_dx = kA * (bbar - abar);
+    } else {
+        // fmaxf before fminf maps NaN to 0
+        const float qa = fminf(fmaxf(rintf(ea), 0.0f), 63.0f);
+        const float qb = fminf(fmaxf(rintf(eb), 0.0f), 63.0f);
+        const uint32_t i = (uint32_t)fminf(fmaxf(rintf(7.0f * x), 0.0f), 7.0f);
+        const int32_t wt = (int32_t)((i * 585u + 32u) >> 6);       // round(64 i / 7)
+        const int32_t A = unquantize<false>((int32_t)qa, 6);
+        const int32_t B = unquantize<false>((int32_t)qb, 6);
+        const int32_t v = ((64 - wt) * A + wt * B + 32) >> 6;
+        const uint32_t y = ((uint32_t)v * 31u) >> 6;
+        r.w = (float)__builtin_bit_cast(_Float16, (uint16_t)y);
+        r.slope = ldexpf(1.0f, h_of_bits(y) - 24);
+        const float xs = (float)wt * (1.0f / 64.0f);
+        r.dy_da = kA * 1024.0f * (1.0f - xs);
+        r.dy_db = kA * 1024.0f * xs;
+        r.dy_dx = kA * 1024.0f * (qb - qa);
+    }
+    return r;
+}
+
+// Where texel t of joint block gb lives: pyramid, block within it, level and
+// position; false for the texels a level below 4x4 does not have.
+struct TexelSite {
+    uint32_t ti, b, x, y, tex;      // tex: texel index in the images
+    bool valid;
+};
+
+__device__ __forceinline__ TexelSite texel_site(const TrainDesc &d, uint32_t gb, uint32_t t)
+{
+    TexelSite s;
+    uint32_t ti = 0;
+    while (ti + 1 < d.n_tex && gb >= d.blk_base[ti + 1]) ++ti;
+    const TrainTexDesc &tx = d.tex[ti];
+    const uint32_t b = gb - d.blk_base[ti];
+    uint32_t l = 0;
+    while (l + 1 < tx.levels && b >= tx.blk_off[l + 1]) ++l;
+    const uint32_t wl = max(tx.w >> l, 1u), hl = max(tx.h >> l, 1u);
+    const uint32_t bxn = (wl + 3u) >> 2;
+    const uint32_t lb = b - tx.blk_off[l];
+    s.ti = ti;
+    s.b = b;
+    s.x = (lb % bxn) * 4u + (t & 3u);
+    s.y = (lb / bxn) * 4u + (t >> 2);
+    s.valid = s.x < wl && s.y < hl;
+    s.tex = tx.tex_off[l] + s.y * wl + s.x;
+    return s;
+}
+
+__device__ __forceinline__ uint32_t subset_of(const TrainTexDesc &tx, uint32_t b, uint32_t t)
+{
+    // partition ids are taken modulo 32
+    return (kTable[kModes * kModeWords + (tx.partitions[b] & 31u)] >> t) & 1u;
+}
+
+template <bool STE>
+__global__ void __launch_bounds__(kTrainThreads) k_train_texels(TrainDesc d)
+{
+    const uint32_t total = d.blk_base[d.n_tex] * 16u;
+    for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < total; g += gridDim.x * blockDim.x) {
+        const uint32_t t = g & 15u;
+        const TexelSite s = texel_site(d, g >> 4, t);
+        if (!s.valid) continue;
+        const TrainTexDesc &tx = d.tex[s.ti];
+        const uint32_t sub = subset_of(tx, s.b, t);
+        const float *e = tx.endpoints + 12u * s.b;
+        const float x = tx.indices[16u * s.b + t];
+        float w[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) w[c] = texel_chan<STE>(e[6u * sub + c], e[6u * sub + 3u + c], x).w;
+        d.texels[s.tex] = make_float4(w[0], w[1], w[2], 0.0f);
+    }
+}
+
+template <bool STE>
+__global__ void __launch_bounds__(kTrainThreads) k_train_blocks(TrainDesc d)
+{
+    // every 16-lane group is one block: total is a multiple of 16, so a group's
+    // lanes enter and leave the loop together
+    const uint32_t total = d.blk_base[d.n_tex] * 16u;
+    for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < total; g += gridDim.x * blockDim.x) {
+        const uint32_t t = g & 15u;
+        const TexelSite s = texel_site(d, g >> 4, t);
+        const TrainTexDesc &tx = d.tex[s.ti];
+        const uint32_t sub = subset_of(tx, s.b, t);
+        const float *e = tx.endpoints + 12u * s.b;
+        float gx = 0.0f;
+        float ge[2][3] = {{0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f}};   // this texel's pair A, B
+        if (s.valid) {
+            const float4 gt = d.g_texels[s.tex];
+            const float gc[3] = {gt.x, gt.y, gt.z};
+            const float x = tx.indices[16u * s.b + t];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const TexelChan r = texel_chan<STE>(e[6u * sub + c], e[6u * sub + 3u + c], x);
+                const float gy = gc[c] * r.slope;
+                gx = fmaf(gy, r.dy_dx, gx);
+                ge[0][c] = gy * r.dy_da;
+                ge[1][c] = gy * r.dy_db;
+            }
+        }
+        tx.g_indices[16u * s.b + t] = gx;
+        // sum over the block's texels, per subset
+        float sum[4][3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            sum[0][c] = sub ? 0.0f : ge[0][c];
+            sum[1][c] = sub ? 0.0f : ge[1][c];
+            sum[2][c] = sub ? ge[0][c] : 0.0f;
+            sum[3][c] = sub ? ge[1][c] : 0.0f;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int m = 1; m < 16; m <<= 1) sum[j][c] += __shfl_xor(sum[j][c], m, 16);
+        if (t < 12) {
+            float v = 0.0f;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) v = (3 * j + c == (int)t) ? sum[j][c] : v;
+            tx.g_endpoints[12u * s.b + t] = v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// queries
+
+// The 32 taps of a query (4 pyramids x 2 levels x 4 texels): texel index and
+// weight (bilinear times trilinear); pyramids past n_tex get weight 0.
+__device__ __forceinline__ void taps(const TrainDesc &d, float u, float v, float s, uint32_t idx[32], float wt[32])
+{
+    const float uf = u - floorf(u), vf = v - floorf(v);          // wrap addressing
+#pragma unroll
+    for (int ti = 0; ti < kMaxTextures; ++ti) {
+        const TrainTexDesc &tx = d.tex[ti < (int)d.n_tex ? ti : 0];
+        const float si = fminf(fmaxf(s + tx.bias, 0.0f), (float)(tx.levels - 1));   // NaN -> 0
+        const uint32_t l0 = (uint32_t)floorf(si);
+        const uint32_t l1 = min(l0 + 1u, tx.levels - 1u);
+        const float lam = si - (float)l0;
+        const float on = ti < (int)d.n_tex ? 1.0f : 0.0f;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const uint32_t l = k ? l1 : l0;
+            const float lw = on * (k ? lam : 1.0f - lam);
+            const uint32_t wl = max(tx.w >> l, 1u), hl = max(tx.h >> l, 1u);
+            const float x = fmaf(uf, (float)wl, -0.5f), y = fmaf(vf, (float)hl, -0.5f);
+            const float x0 = floorf(x), y0 = floorf(y);
+            const float fx = x - x0, fy = y - y0;
+            const uint32_t xa = (uint32_t)(int)x0 & (wl - 1u), xb = (xa + 1u) & (wl - 1u);
+            const uint32_t ya = (uint32_t)(int)y0 & (hl - 1u), yb = (ya + 1u) & (hl - 1u);
+            const uint32_t base = tx.tex_off[l];
+            const int o = 8 * ti + 4 * k;
+            idx[o + 0] = base + ya * wl + xa;
+            idx[o + 1] = base + ya * wl + xb;
+            idx[o + 2] = base + yb * wl + xa;
+            idx[o + 3] = base + yb * wl + xb;
+            wt[o + 0] = lw * (1.0f - fx) * (1.0f - fy);
+            wt[o + 1] = lw * fx * (1.0f - fy);
+            wt[o + 2] = lw * (1.0f - fx) * fy;
+            wt[o + 3] = lw * fx * fy;
+        }
+    }
+}
+
+__device__ __forceinline__ void features(const TrainDesc &d, float u, float v, float s, float z[12])
+{
+    uint32_t idx[32];
+    float wt[32];
+    taps(d, u, v, s, idx, wt);
+#pragma unroll
+    for (int i = 0; i < 12; ++i) z[i] = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 32; ++k) {
+        const float4 tv = d.texels[idx[k]];
+        const int t = k / 8;
+        z[3 * t + 0] = fmaf(wt[k], tv.x, z[3 * t + 0]);
+        z[3 * t + 1] = fmaf(wt[k], tv.y, z[3 * t + 1]);
+        z[3 * t + 2] = fmaf(wt[k], tv.z, z[3 * t + 2]);
+    }
+}
+
+typedef const __attribute__((address_space(4))) float const_float;
+
+// Forward MLP with the hidden activations kept (act[l] = output of hidden layer l).
+template <int H, int NH>
+__device__ __forceinline__ void mlp_forward(const TrainDesc &d, const float z[12], float act[NH][H],
+                                            float out[kMaxOut])
+{
+    const_float *P = (const_float *)d.params;
+    const uint32_t n0 = d.dims[0];
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+        float acc = P[d.b_off[0] + j];
+#pragma unroll
+        for (int i = 0; i < 12; ++i)
+            if ((uint32_t)i < n0) acc = fmaf(P[d.w_off[0] + j * n0 + i], z[i], acc);
+        act[0][j] = fmaxf(acc, 0.0f);
+    }
+#pragma unroll
+    for (int l = 1; l < NH; ++l)
+#pragma unroll
+        for (int j = 0; j < H; ++j) {
+            float acc = P[d.b_off[l] + j];
+#pragma unroll
+            for (int i = 0; i < H; ++i) acc = fmaf(P[d.w_off[l] + j * H + i], act[l - 1][i], acc);
+            act[l][j] = fmaxf(acc, 0.0f);
+        }
+    const uint32_t c = d.dims[NH + 1];
+#pragma unroll
+    for (int j = 0; j < kMaxOut; ++j) {
+        float acc = 0.0f;
+        if ((uint32_t)j < c) {
+            acc = P[d.b_off[NH] + j];
+#pragma unroll
+            for (int i = 0; i < H; ++i) acc = fmaf(P[d.w_off[NH] + j * H + i], act[NH - 1][i], acc);
+        }
+        out[j] = acc;
+    }
+}
+
+template <int H, int NH>
+__global__ void __launch_bounds__(kTrainThreads) k_train_forward(TrainDesc d, const float *queries, uint32_t n,
+                                                                 float *out)
+{
+    const uint32_t c = d.dims[NH + 1];
+    for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
+        float z[12], act[NH][H], o[kMaxOut];
+        features(d, queries[3u * q], queries[3u * q + 1u], queries[3u * q + 2u], z);
+        mlp_forward<H, NH>(d, z, act, o);
+#pragma unroll
+        for (int j = 0; j < kMaxOut; ++j)
+            if ((uint32_t)j < c) out[(size_t)q * c + j] = o[j];
+    }
+}
+
+// Per-lane share of a layer's parameter gradients: entry e = lane + 64 k of
+// the layer's W (row-major) then b.
+constexpr int entries_per_lane(int n_in, int n_out) { return (n_out * (n_in + 1) + 63) / 64; }
+
+// acc[k] += sum over the wave's 64 queries of delta[q][j] * a[q][i] for the
+// lane's entries; a[q][n_in] holds 1 for the bias entries.
+template <int K>
+__device__ __forceinline__ void accumulate(float acc[K], const float (*a)[kTrainMaxHidden + 1],
+                                           const float (*dl)[kTrainMaxHidden], uint32_t n_in, uint32_t n_out,
+                                           uint32_t lane)
+{
+    const uint32_t n_w = n_in * n_out;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const uint32_t e = lane + 64u * (uint32_t)k;
+        if (e >= n_w + n_out) continue;
+        const uint32_t j = e < n_w ? e / n_in : e - n_w;
+        const uint32_t i = e < n_w ? e - j * n_in : n_in;
+        float s = 0.0f;
+#pragma unroll 4
+        for (int q = 0; q < 64; ++q) s = fmaf(dl[q][j], a[q][i], s);
+        acc[k] += s;
+    }
+}
+
+template <int K>
+__device__ __forceinline__ void flush(const float acc[K], float *g, uint32_t n_in, uint32_t n_out, uint32_t lane)
+{
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const uint32_t e = lane + 64u * (uint32_t)k;
+        if (e < n_out * (n_in + 1u)) unsafeAtomicAdd(g + e, acc[k]);
+    }
+}
+
+template <int H, int NH>
+__global__ void __launch_bounds__(kTrainThreads) k_train_backward(TrainDesc d, const float *queries, uint32_t n,
+                                                                  const float *grad_out)
+{
+    constexpr int K0 = entries_per_lane(12, H);
+    constexpr int KH = entries_per_lane(H, H);
+    constexpr int KL = entries_per_lane(H, kMaxOut);
+    __shared__ float lds_a[kTrainWaves][64][kTrainMaxHidden + 1];
+    __shared__ float lds_d[kTrainWaves][64][kTrainMaxHidden];
+
+    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+    const uint32_t n0 = d.dims[0], c = d.dims[NH + 1];
+    const_float *P = (const_float *)d.params;
+    float acc0[K0], accH[NH > 1 ? NH - 1 : 1][KH], accL[KL];
+#pragma unroll
+    for (int k = 0; k < K0; ++k) acc0[k] = 0.0f;
+#pragma unroll
+    for (int l = 0; l < (NH > 1 ? NH - 1 : 1); ++l)
+#pragma unroll
+        for (int k = 0; k < KH; ++k) accH[l][k] = 0.0f;
+#pragma unroll
+    for (int k = 0; k < KL; ++k) accL[k] = 0.0f;
+
+    float (*a)[kTrainMaxHidden + 1] = lds_a[wv];
+    float (*dl)[kTrainMaxHidden] = lds_d[wv];
+    const uint32_t n_chunks = (n + 63u) / 64u;
+    for (uint32_t ch = blockIdx.x * kTrainWaves + wv; ch < n_chunks; ch += gridDim.x * kTrainWaves) {
+        const uint32_t q = ch * 64u + lane;
+        const bool live = q < n;
+        const float u = live ? queries[3u * q] : 0.0f;
+        const float v = live ? queries[3u * q + 1u] : 0.0f;
+        const float s = live ? queries[3u * q + 2u] : 0.0f;
+        float z[12], act[NH][H], o[kMaxOut];
+        features(d, u, v, s, z);
+        mlp_forward<H, NH>(d, z, act, o);
+        float delta[kTrainMaxHidden];
+#pragma unroll
+        for (int j = 0; j < kTrainMaxHidden; ++j)
+            delta[j] = (live && j < kMaxOut && (uint32_t)j < c) ? grad_out[(size_t)q * c + j] : 0.0f;
+
+        // output layer: W[c][H]
+#pragma unroll
+        for (int i = 0; i < H; ++i) a[lane][i] = act[NH - 1][i];
+        a[lane][H] = 1.0f;
+#pragma unroll
+        for (int j = 0; j < kMaxOut; ++j) dl[lane][j] = delta[j];
+        wave_sync_lds();
+        accumulate<KL>(accL, a, dl, H, c, lane);
+        wave_sync_lds();
+        // back through the hidden layers: delta of hidden layer l's pre-activation
+#pragma unroll
+        for (int l = NH - 1; l >= 0; --l) {
+            const uint32_t rows = l == NH - 1 ? c : H;           // outputs of layer l + 1
+            const uint32_t wo = d.w_off[l + 1], stride = H;
+            float g[H];
+#pragma unroll
+            for (int i = 0; i < H; ++i) {
+                float acc = 0.0f;
+#pragma unroll
+                for (int j = 0; j < (l == NH - 1 ? kMaxOut : H); ++j)
+                    if ((uint32_t)j < rows) acc = fmaf(P[wo + j * stride + i], delta[j], acc);
+                g[i] = act[l][i] > 0.0f ? acc : 0.0f;
+            }
+#pragma unroll
+            for (int i = 0; i < H; ++i) delta[i] = g[i];
+            // parameters of layer l: inputs are act[l - 1] (or z), outputs delta
+            const uint32_t n_in = l == 0 ? n0 : H;
+            if (l == 0) {
+#pragma unroll
+                for (int i = 0; i < 12; ++i) a[lane][i] = z[i];
+            } else {
+#pragma unroll
+                for (int i = 0; i < H; ++i) a[lane][i] = act[l > 0 ? l - 1 : 0][i];
+            }
+            a[lane][n_in] = 1.0f;
+#pragma unroll
+            for (int j = 0; j < H; ++j) dl[lane][j] = delta[j];
+            wave_sync_lds();
+            if (l == 0) accumulate<K0>(acc0, a, dl, n0, H, lane);
+            else accumulate<KH>(accH[l > 0 ? l - 1 : 0], a, dl, H, H, lane);
+            wave_sync_lds();
+        }
+        // dL/dz = W_0^T delta, then onto the 32 taps
+        float dz[12];
+#pragma unroll
+        for (int i = 0; i < 12; ++i) {
+            float acc = 0.0f;
+            if ((uint32_t)i < n0)
+#pragma unroll
+                for (int j = 0; j < H; ++j) acc = fmaf(P[d.w_off[0] + j * n0 + i], delta[j], acc);
+            dz[i] = acc;
+        }
+        if (live) {
+            uint32_t idx[32];
+            float wt[32];
+            taps(d, u, v, s, idx, wt);
+#pragma unroll
+            for (int k = 0; k < 32; ++k) {
+                const int t = k / 8;
+                if (t < (int)d.n_tex) {
+                    float *gp = reinterpret_cast<float *>(d.g_texels + idx[k]);
+                    unsafeAtomicAdd(gp + 0, wt[k] * dz[3 * t + 0]);
+                    unsafeAtomicAdd(gp + 1, wt[k] * dz[3 * t + 1]);
+                    unsafeAtomicAdd(gp + 2, wt[k] * dz[3 * t + 2]);
+                }
+            }
+        }
+    }
+    flush<K0>(acc0, d.g_params + d.w_off[0], n0, H, lane);
+#pragma unroll
+    for (int l = 1; l < NH; ++l) flush<KH>(accH[l - 1], d.g_params + d.w_off[l], H, H, lane);
+    flush<KL>(accL, d.g_params + d.w_off[NH], H, c, lane);
+}
+
+unsigned grid_for(size_t work, unsigned per_block, unsigned cap)
+{
+    const size_t g = (work + per_block - 1) / per_block;
+    return (unsigned)(g < 1 ? 1 : (g > cap ? cap : g));
+}
+
+hipError_t launch_texels(const TrainDesc &d, hipStream_t s)
+{
+    const unsigned grid = grid_for((size_t)d.blk_base[d.n_tex] * 16u, kTrainThreads, 16384);
+    if (d.ste) k_train_texels<true><<<grid, kTrainThreads, 0, s>>>(d);
+    else k_train_texels<false><<<grid, kTrainThreads, 0, s>>>(d);
+    return hipGetLastError();
+}
+
+template <int H, int NH>
+hipError_t forward_hn(const TrainDesc &d, const float *queries, uint32_t n, float *out, hipStream_t s)
+{
+    k_train_forward<H, NH><<<grid_for(n, kTrainThreads, 8192), kTrainThreads, 0, s>>>(d, queries, n, out);
+    return hipGetLastError();
+}
+
+template <int H, int NH>
+hipError_t backward_hn(const TrainDesc &d, const float *queries, uint32_t n, const float *grad_out, hipStream_t s)
+{
+    // a few waves per CU: every wave flushes its parameter sums once
+    const unsigned grid = grid_for((n + 63u) / 64u, kTrainWaves, 512);
+    k_train_backward<H, NH><<<grid, kTrainThreads, 0, s>>>(d, queries, n, grad_out);
+    return hipGetLastError();
+}
+
+#define BCF_TRAIN_DISPATCH(fn, ...)                                                           \
+    do {                                                                                      \
+        const uint32_t H = d.dims[1], NH = d.n_layers - 1;                                    \
+        if (H == 16 && NH == 1) return fn<16, 1>(d, __VA_ARGS__);                             \
+        if (H == 16 && NH == 2) return fn<16, 2>(d, __VA_ARGS__);                             \
+        if (H == 16 && NH == 3) return fn<16, 3>(d, __VA_ARGS__);                             \
+        if (H == 32 && NH == 1) return fn<32, 1>(d, __VA_ARGS__);                             \
+        if (H == 32 && NH == 2) return fn<32, 2>(d, __VA_ARGS__);                             \
+        if (H == 32 && NH == 3) return fn<32, 3>(d, __VA_ARGS__);                             \
+        return hipErrorInvalidValue;                                                          \
+    } while (0)
+
+hipError_t dispatch_forward(const TrainDesc &d, const float *queries, uint32_t n, float *out, hipStream_t s)
+{
+    BCF_TRAIN_DISPATCH(forward_hn, queries, n, out, s);
+}
+
+hipError_t dispatch_backward(const TrainDesc &d, const float *queries, uint32_t n, const float *grad_out,
+                             hipStream_t s)
+{
+    BCF_TRAIN_DISPATCH(backward_hn, queries, n, grad_out, s);
+}
+
+#undef BCF_TRAIN_DISPATCH
+
+}  // namespace
+
+hipError_t launch_train_forward(const TrainDesc &d, const float *queries, size_t n, float *out, hipStream_t s)
+{
+    hipError_t e = launch_texels(d, s);
+    if (e != hipSuccess || n == 0) return e;
+    return dispatch_forward(d, queries, (uint32_t)n, out, s);
+}
+
+hipError_t launch_train_backward(const TrainDesc &d, const float *queries, size_t n, const float *grad_out,
+                                 hipStream_t s)
+{
+    hipError_t e = launch_texels(d, s);
+    if (e != hipSuccess) return e;
+    k_train_zero<<<grid_for((size_t)d.n_texels * 4u, 256, 8192), 256, 0, s>>>(
+        reinterpret_cast<float *>(d.g_texels), d.n_texels * 4u);
+    k_train_zero<<<grid_for(d.n_params, 256, 64), 256, 0, s>>>(d.g_params, d.n_params);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (n > 0 && (e = dispatch_backward(d, queries, (uint32_t)n, grad_out, s)) != hipSuccess) return e;
+    const unsigned grid = grid_for((size_t)d.blk_base[d.n_tex] * 16u, kTrainThreads, 16384);
+    if (d.ste) k_train_blocks<true><<<grid, kTrainThreads, 0, s>>>(d);
+    else k_train_blocks<false><<<grid, kTrainThreads, 0, s>>>(d);
+    return hipGetLastError();
+}
+
+}  // namespace bcf

@@ -1,0 +1,52 @@
+// Training-time decode (Section 4.2, "Trainable BC6 decompression"): the
+// descriptors shared by the host API (train_api.cpp) and the kernels
+// (train.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "internal.hpp"
+
+namespace bcf {
+
+constexpr int kTrainMaxHidden = 32;
+
+// One pyramid of continuous two-subset blocks (6-bit endpoints, 3-bit
+// indices, fixed partitions), all levels back to back.
+struct TrainTexDesc {
+    const float *endpoints;        // [n_blocks][4][3]
+    const float *indices;          // [n_blocks][16]
+    const uint8_t *partitions;     // [n_blocks]
+    float *g_endpoints;            // backward outputs, same layouts
+    float *g_indices;
+    uint32_t w, h, levels;
+    float bias;
+    uint32_t n_blocks;
+    uint32_t blk_off[kMaxLevels];  // first block of each level
+    uint32_t tex_off[kMaxLevels];  // first texel of each level in the texel images (pitch w_l)
+};
+
+struct TrainDesc {
+    TrainTexDesc tex[kMaxTextures];
+    uint32_t n_tex;
+    uint32_t ste;                  // 1: straight-through (exact decode forward)
+    uint32_t blk_base[kMaxTextures + 1];   // first block of each pyramid in a joint numbering
+    float4 *texels;                // texel values (r, g, b, 0)
+    float4 *g_texels;              // their gradients
+    uint32_t n_texels;
+    const float *params;           // per layer W[out][in] row-major, then b[out]
+    float *g_params;
+    uint32_t n_params;
+    uint32_t dims[5];
+    uint32_t n_layers;
+    uint32_t w_off[4], b_off[4];   // float offsets of each layer's W and b in params
+};
+
+hipError_t launch_train_forward(const TrainDesc &d, const float *queries, size_t n, float *out,
+                                hipStream_t s);
+hipError_t launch_train_backward(const TrainDesc &d, const float *queries, size_t n, const float *grad_out,
+                                 hipStream_t s);
+
+}  // namespace bcf

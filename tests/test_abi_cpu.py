@@ -151,3 +151,59 @@ def test_error_text_is_thread_local(bcf):
     t.join()
     assert "levels" in seen["other"]
     assert "n_textures" in bcf.lib.bcf_last_error().decode()
+
+
+def train_material(bcf, n_tex=4, res=32, levels=6, dims=(12, 32, 32, 10), ste=0, ptr=FAKE, bias=0.0):
+    from paper_2311_16121_amd._lib import _TrainMaterial, _TrainTexture
+    tex = (_TrainTexture * max(n_tex, 1))()
+    for i in range(n_tex):
+        w, h = (res, res) if isinstance(res, int) else res
+        tex[i] = _TrainTexture(w, h, levels, bias, ptr, ptr, ptr)
+    d = (C.c_uint32 * len(dims))(*dims)
+    m = _TrainMaterial(n_tex, tex, len(dims) - 1, d, FAKE, ste)
+    m._keep = (tex, d)
+    return m
+
+
+def test_train_workspace_size(bcf):
+    n = C.c_size_t(0)
+    assert bcf.lib.bcf_train_workspace_size(C.byref(train_material(bcf)), C.byref(n)) == 0
+    texels = 4 * sum(max(32 >> l, 1) ** 2 for l in range(6))
+    assert n.value == 2 * ((texels * 16 + 255) // 256 * 256)
+
+
+@pytest.mark.parametrize("kwargs,status,msg", [
+    (dict(n_tex=0), 1, "n_textures"),
+    (dict(res=(48, 32)), 1, "power-of-two"),
+    (dict(levels=7), 1, "levels"),
+    (dict(ptr=0), 1, "NULL"),
+    (dict(ste=2), 1, "straight_through"),
+    (dict(dims=(12, 64, 10)), 2, "16 or 32"),
+    (dict(dims=(12, 32, 16, 10)), 2, "16 or 32"),
+    (dict(dims=(9, 32, 10)), 1, "dims[0]"),
+    (dict(dims=(12, 32, 17)), 2, "output"),
+    (dict(dims=(12, 10)), 2, "n_layers"),
+    (dict(bias=float("inf")), 1, "lod_bias"),
+])
+def test_train_material_validation(bcf, kwargs, status, msg):
+    n = C.c_size_t(0)
+    st = bcf.lib.bcf_train_workspace_size(C.byref(train_material(bcf, **kwargs)), C.byref(n))
+    assert st == status
+    assert msg in bcf.lib.bcf_last_error().decode()
+
+
+def test_train_call_argument_checks(bcf):
+    m = train_material(bcf)
+    assert bcf.lib.bcf_train_workspace_size(C.byref(m), None) == 1
+    # forward: n == 0 touches nothing
+    assert bcf.lib.bcf_train_forward(C.byref(m), None, None, 0, None, None) == 0
+    assert bcf.lib.bcf_train_forward(C.byref(m), C.c_void_p(FAKE + 8), C.c_void_p(FAKE), 5, C.c_void_p(FAKE),
+                                     None) == 1
+    assert bcf.lib.bcf_train_forward(C.byref(m), C.c_void_p(FAKE), None, 5, C.c_void_p(FAKE), None) == 1
+    ptrs = (C.c_void_p * 4)(*([FAKE] * 4))
+    nulls = (C.c_void_p * 4)(FAKE, FAKE, 0, FAKE)
+    args = [C.byref(m), C.c_void_p(FAKE), C.c_void_p(FAKE), 5, C.c_void_p(FAKE)]
+    assert bcf.lib.bcf_train_backward(*args, None, ptrs, C.c_void_p(FAKE), None) == 1
+    assert bcf.lib.bcf_train_backward(*args, ptrs, nulls, C.c_void_p(FAKE), None) == 1
+    assert "texture 2" in bcf.lib.bcf_last_error().decode()
+    assert bcf.lib.bcf_train_backward(*args, ptrs, ptrs, None, None) == 1

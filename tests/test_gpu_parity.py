@@ -261,7 +261,7 @@ def test_full_frame_sampled_outputs(bcf):
 
 def test_unpack_then_decode_unpacked_equals_decode(bcf):
     texs, sizes, lv, params, bias, host = make(64, 7, (12, 32, 32, 10), "B", seed=21)
-    q = synth.uniform_queries(5000, 7, synth.rng(22))
+    q = synth.uniform_queries(5000, synth.rng(22), 6.0)
     mat = bcf.Material.from_host(texs, sizes, lv, (12, 32, 32, 10), params, bias)
     qd = dev(q)
     for p in ("FP32", "FP16"):
