@@ -155,6 +155,193 @@ def cpu_baseline(material, queries, budget_s):
                       f"from the same frame; {dt:.1f} s on {threads} threads"}
 
 
+def bench_batch(args):
+    """64 materials (base 512..4096^2, four pyramids each, full chains), MLP
+    12-32-32-10 FP16 each, query counts log-uniform in [2^14, 2^22], u, v
+    uniform, s uniform over each chain. A step unpacks every material and
+    decodes every query in one persistent launch, replayed from a graph."""
+    import torch
+
+    import paper_2311_16121_amd as bcf
+    import synth
+
+    spec = synth.batch_spec()
+    pool = synth.block_pool()
+    log(f"generating {spec.n_materials} materials, {sum(spec.counts)} queries")
+    mats, qparts, counts_texels, alg_texels = [], [], 0, 0
+    for k in range(spec.n_materials):
+        m = synth.batch_material(spec, k, pool)
+        mats.append(bcf.Material.from_host(m.textures, m.res, m.levels, m.dims, m.params))
+        q = synth.batch_queries(spec, k)
+        geo = [((r, r), L, b) for r, L, b in zip(m.res, m.levels, m.lod_bias)]
+        alg_texels += unique_texels(geo, q)
+        qparts.append(torch.from_numpy(q).cuda())
+        del m
+    qd = torch.cat(qparts)
+    del qparts
+    n = qd.shape[0]
+    offsets = torch.from_numpy(spec.offsets().astype(np.int32)).cuda()
+    batch = bcf.Batch(mats, bcf.Precision.FP16)
+    out = torch.empty((n, spec.dims[-1]), dtype=torch.float32, device="cuda")
+    batch.unpack()
+    log("tuning")
+    plan, tuned_ms = batch.tune(qd, offsets, out=out)
+    stream = torch.cuda.current_stream()
+
+    # per-kernel times with events (eager)
+    def eager(steps):
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+        torch.cuda.synchronize()
+        for e in ev:
+            e[0].record(stream)
+            batch.unpack(stream)
+            e[1].record(stream)
+            batch.decode(qd, offsets, out=out, plan=plan, stream=stream)
+            e[2].record(stream)
+        torch.cuda.synchronize()
+        return (sum(e[0].elapsed_time(e[1]) for e in ev) / steps, sum(e[1].elapsed_time(e[2]) for e in ev) / steps)
+
+    eager(args.warmup)
+    unpack_ms, decode_ms = eager(args.steps)
+    # the step as one graph
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(graph, stream=side):
+            batch.unpack()
+            batch.decode(qd, offsets, out=out, plan=plan)
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        graph.replay()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for _ in range(args.steps):
+        graph.replay()
+    end.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end) / args.steps
+    c = spec.dims[-1]
+    frame_bytes = n * 12 + n * 4 * c + 8 * alg_texels
+    blocks = sum(4 * synth.chain_blocks(r, r, synth.full_levels(r, r)) for r in spec.res)
+    unpack_bytes = blocks * (16 + 16 * 8)
+    achieved = frame_bytes / (decode_ms * 1e-3) / 1e9
+    line = {
+        "metric": "decoded queries/s, 64 materials in one persistent graph-captured launch (FP16-MFMA MLP)",
+        "value": n / (ms * 1e-3),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f16",
+        "data": "synthetic",
+        "config": {"workload": "batch64: 64 materials, base 512..4096^2 (4 pyramids, full chains), MLP 12-32-32-10 "
+                               "FP16 per material, queries log-uniform in [2^14, 2^22] per material",
+                   "queries": n, "materials": spec.n_materials, "texture_bytes": blocks * 16,
+                   "plan": {"workgroups": plan[0], "interleave": plan[1], "tuned_decode_ms": tuned_ms}},
+        "roofline": {"bound": "hbm", "kernel": "k_batch (fp16)", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "alg_bytes_per_launch": frame_bytes, "launch_ms": decode_ms},
+        "kernels": {"unpack_all": {"launch_ms": unpack_ms, "alg_bytes": unpack_bytes,
+                                   "achieved": unpack_bytes / (unpack_ms * 1e-3) / 1e9}},
+        "counts": {"unique_texels": alg_texels, "all_blocks": blocks},
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_train(args):
+    """One training step (Section 5.1) per timed step: the straight-through
+    forward of four 1024^2 trainable pyramids (full chains, LOD bias -1 against
+    the 2048^2 reference), MLP 12-32-32-10, on 2^20 random (u, v, s) samples;
+    the mean squared error against the procedural reference sampled bicubically
+    on two mips; the backward to every block parameter and weight; one Adam
+    update."""
+    import torch
+
+    import paper_2311_16121_amd as bcf
+    import synth
+
+    dims = (12, 32, 32, 10)
+    n = 1 << 20
+    log("generating the reference and the trainable pyramids")
+    ends, idxs, parts, L, params = synth.train_problem(1024, dims)
+    chain = synth.procedural_target(2048)
+    q = synth.uniform_queries(n, synth.rng(synth.SEED_QUERIES), float(len(chain) - 1))
+    target = torch.from_numpy(synth.sample_target(chain, q)).cuda()
+    del chain
+    qd = torch.from_numpy(q).cuda()
+    geo = bcf.TrainGeometry([1024] * 4, [L] * 4, [torch.from_numpy(p).cuda() for p in parts], dims, [-1.0] * 4,
+                            straight_through=True)
+    leaves = [torch.from_numpy(e).cuda().requires_grad_(True) for e in ends] + \
+             [torch.from_numpy(x).cuda().requires_grad_(True) for x in idxs]
+    w = torch.from_numpy(params).cuda().requires_grad_(True)
+    opt = torch.optim.Adam([{"params": leaves, "lr": 0.02}, {"params": [w], "lr": 2e-3}])
+
+    def step():
+        out = bcf.train_decode(geo, leaves[:4], leaves[4:], w, qd)
+        loss = torch.mean((out - target) ** 2)
+        opt.zero_grad(set_to_none=False)
+        loss.backward()
+        opt.step()
+        return loss
+
+    losses = [float(step())]
+    for _ in range(max(args.warmup - 1, 0)):
+        step()
+    stream = torch.cuda.current_stream()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for _ in range(args.steps):
+        loss = step()
+    end.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end) / args.steps
+    losses.append(float(loss))
+    # the two native calls alone
+    with torch.no_grad():
+        e = [x.detach() for x in leaves]
+        go = torch.randn((n, dims[-1]), device="cuda")
+        t0, t1, t2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        bcf.train_forward(geo, e[:4], e[4:], w.detach(), qd)
+        bcf.train_backward(geo, e[:4], e[4:], w.detach(), qd, go)
+        torch.cuda.synchronize()
+        t0.record(stream)
+        for _ in range(5):
+            bcf.train_forward(geo, e[:4], e[4:], w.detach(), qd)
+        t1.record(stream)
+        for _ in range(5):
+            bcf.train_backward(geo, e[:4], e[4:], w.detach(), qd, go)
+        t2.record(stream)
+        torch.cuda.synchronize()
+    line = {
+        "metric": "training samples/s (straight-through forward + backward + Adam)",
+        "value": n / (ms * 1e-3),
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "train: 4 x 1024^2 trainable BC6H pyramids (11 levels, two-subset 6-bit endpoint / "
+                               "3-bit index blocks), MLP 12-32-32-10, batch 2^20, procedural 2048^2 10-channel "
+                               "reference", "batch": n,
+                   "parameters": int(sum(x.numel() for x in leaves) + w.numel())},
+        "loss": {"first": losses[0], "last": losses[-1]},
+        "kernels": {"train_forward_ms": t0.elapsed_time(t1) / 5, "train_backward_ms": t1.elapsed_time(t2) / 5},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -164,6 +351,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first run a plain copy of this many MiB (to scale memory counters)")
+    ap.add_argument("--workload", default="frame4k", choices=("frame4k", "batch64", "train"),
+                    help="frame4k: the full-frame decode (default); batch64: 64 materials in one launch; "
+                         "train: a straight-through training step")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -176,6 +366,10 @@ def main():
     import synth
 
     torch.cuda.set_device(0)
+    if args.workload == "batch64":
+        return bench_batch(args)
+    if args.workload == "train":
+        return bench_train(args)
     wl = synth.WORKLOADS["frame4k"]
     log("generating workload")
     m = synth.workload_material(wl, variant="B")

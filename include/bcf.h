@@ -116,7 +116,9 @@ bcf_status bcf_prepare(const bcf_material *m, bcf_precision p, void *ws,
  * out (device, [n][dims[n_layers]] binary32, row-major). s is the scale of
  * eq. (9) before the per-texture bias. grid_width > 0 declares that the
  * queries are a row-major image of that many columns (a frame in scanline
- * order); 0 means no 2D structure. Results do not depend on grid_width.
+ * order; the last row may be partial), which lets the decoder walk it in
+ * square tiles whose queries share texels; 0 means no 2D structure. Results
+ * do not depend on grid_width.
  * n == 0 is a no-op. out must not overlap queries, ws or the material.
  * Non-finite query components produce unspecified values but never an
  * out-of-bounds access. Same as bcf_unpack followed by bcf_decode_unpacked
@@ -156,6 +158,58 @@ bcf_status bcf_calibrate(const bcf_material *m, void *ws, const float *queries, 
  * integer form). Reserved mode codes decode to zeros. */
 bcf_status bcf_decode_blocks(const void *blocks, size_t n_blocks, uint32_t is_signed,
                              uint16_t *halves, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Many materials in one launch (Section 5.2 decodes every material of a frame
+ * with its own features and weights; here all of them go through one
+ * persistent kernel).
+ *
+ * A batch is an array of n_mats materials (1..4096) that share one MLP shape
+ * (dims) and run at BCF_FP16 or BCF_FP32; pyramid sizes, level counts, biases
+ * and signedness may differ. Material k's queries are rows offsets[k] ..
+ * offsets[k+1]-1 of one concatenated query array, and its outputs the same
+ * rows of out. offsets is a DEVICE array of n_mats + 1 uint32 values, read by
+ * the kernels: a captured graph replays with whatever the caller has written
+ * there since. The kernels clamp every offset to [0, n_total] (n_total = rows
+ * of queries and out), treat a decreasing pair as an empty material and decode
+ * at most 2^25 queries per material; rows no material covers are not written.
+ * ------------------------------------------------------------------------ */
+
+/* Launch shape of bcf_decode_batch (bcf_tune_batch picks one). */
+typedef struct {
+    uint32_t workgroups;   /* persistent workgroups of 256 threads (rounded up to a
+                              multiple of 8); 0 = a default from n_total */
+    uint32_t interleave;   /* 1: the waves on one XCD take interleaved work items;
+                              0: each wave a contiguous range */
+} bcf_batch_plan;
+
+/* Workspace bytes for the batch (256-byte aligned start). */
+bcf_status bcf_batch_workspace_size(const bcf_material *mats, uint32_t n_mats, bcf_precision p,
+                                    size_t *ws_bytes);
+
+/* Converts every material's MLP into the workspace and writes the batch's
+ * material table. Synchronises `stream` (the table is copied from host
+ * memory); not for graph capture. */
+bcf_status bcf_prepare_batch(const bcf_material *mats, uint32_t n_mats, bcf_precision p, void *ws,
+                             size_t ws_bytes, void *stream);
+
+/* bcf_unpack for every material of the batch (one launch per material). */
+bcf_status bcf_unpack_batch(const bcf_material *mats, uint32_t n_mats, void *ws, void *stream);
+
+/* Decodes every material's queries in one persistent launch (after a small
+ * launch that turns offsets into work items). Asynchronous and free of host
+ * synchronisation and allocation, so it can be captured in a graph together
+ * with bcf_unpack_batch. plan may be NULL. */
+bcf_status bcf_decode_batch(const bcf_material *mats, uint32_t n_mats, bcf_precision p, void *ws,
+                            const float *queries, const uint32_t *offsets, uint32_t n_total,
+                            float *out, const bcf_batch_plan *plan, void *stream);
+
+/* Autotuner: runs bcf_decode_batch over a set of launch shapes on these
+ * inputs, timing each with events, and returns the fastest in *best (and its
+ * time in *best_ms when not NULL). Synchronises `stream`; out is overwritten. */
+bcf_status bcf_tune_batch(const bcf_material *mats, uint32_t n_mats, bcf_precision p, void *ws,
+                          const float *queries, const uint32_t *offsets, uint32_t n_total,
+                          float *out, bcf_batch_plan *best, float *best_ms, void *stream);
 
 /* ------------------------------------------------------------------------
  * Training-time decode (Section 4.2, "Trainable BC6 decompression"; the

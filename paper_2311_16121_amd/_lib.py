@@ -38,6 +38,10 @@ class _Material(C.Structure):
                 ("params", C.c_void_p), ("is_signed", C.c_uint32), ("act_absmax", C.c_void_p)]
 
 
+class _BatchPlan(C.Structure):
+    _fields_ = [("workgroups", C.c_uint32), ("interleave", C.c_uint32)]
+
+
 class _TrainTexture(C.Structure):
     _fields_ = [("width", C.c_uint32), ("height", C.c_uint32), ("levels", C.c_uint32),
                 ("lod_bias", C.c_float), ("endpoints", C.c_void_p), ("indices", C.c_void_p),
@@ -71,6 +75,18 @@ def _load():
     L.bcf_calibrate.restype = C.c_int
     L.bcf_calibrate.argtypes = [C.POINTER(_Material), C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p,
                                 C.c_void_p]
+    L.bcf_batch_workspace_size.restype = C.c_int
+    L.bcf_batch_workspace_size.argtypes = [C.POINTER(_Material), C.c_uint32, C.c_int, C.POINTER(C.c_size_t)]
+    L.bcf_prepare_batch.restype = C.c_int
+    L.bcf_prepare_batch.argtypes = [C.POINTER(_Material), C.c_uint32, C.c_int, C.c_void_p, C.c_size_t, C.c_void_p]
+    L.bcf_unpack_batch.restype = C.c_int
+    L.bcf_unpack_batch.argtypes = [C.POINTER(_Material), C.c_uint32, C.c_void_p, C.c_void_p]
+    L.bcf_decode_batch.restype = C.c_int
+    L.bcf_decode_batch.argtypes = [C.POINTER(_Material), C.c_uint32, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.c_uint32, C.c_void_p, C.POINTER(_BatchPlan), C.c_void_p]
+    L.bcf_tune_batch.restype = C.c_int
+    L.bcf_tune_batch.argtypes = [C.POINTER(_Material), C.c_uint32, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
+                                 C.c_uint32, C.c_void_p, C.POINTER(_BatchPlan), C.POINTER(C.c_float), C.c_void_p]
     L.bcf_train_workspace_size.restype = C.c_int
     L.bcf_train_workspace_size.argtypes = [C.POINTER(_TrainMaterial), C.POINTER(C.c_size_t)]
     L.bcf_train_forward.restype = C.c_int
@@ -91,7 +107,8 @@ lib = _load()
 
 EXPORTED = ("bcf_abi_version", "bcf_last_error", "bcf_texture_bytes", "bcf_prepare",
             "bcf_decode", "bcf_unpack", "bcf_decode_unpacked", "bcf_calibrate", "bcf_decode_blocks",
-            "bcf_train_workspace_size", "bcf_train_forward", "bcf_train_backward")
+            "bcf_batch_workspace_size", "bcf_prepare_batch", "bcf_unpack_batch", "bcf_decode_batch",
+            "bcf_tune_batch", "bcf_train_workspace_size", "bcf_train_forward", "bcf_train_backward")
 
 
 def _check(status: int, what: str):
@@ -257,6 +274,75 @@ def decode_blocks(blocks, signed: bool = False, stream=None):
     _check(lib.bcf_decode_blocks(C.c_void_p(b.data_ptr()), n, int(signed), C.c_void_p(out.data_ptr()),
                                  _stream(stream)), "bcf_decode_blocks")
     return out
+
+
+# ---------------------------------------------------------------------------
+# many materials in one launch (include/bcf.h, bcf_*_batch)
+
+class Batch:
+    """Materials served together: one workspace, one persistent decode launch.
+
+    materials: list of Material (one MLP shape); precision FP16 or FP32.
+    """
+
+    def __init__(self, materials, precision=Precision.FP16, stream=None):
+        import torch
+        self.materials = list(materials)
+        self.precision = Precision(precision)
+        n = len(self.materials)
+        self.c = (_Material * n)(*[m.c for m in self.materials])
+        nbytes = C.c_size_t(0)
+        _check(lib.bcf_batch_workspace_size(self.c, n, int(self.precision), C.byref(nbytes)),
+               "bcf_batch_workspace_size")
+        ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.materials[0].params.device)
+        off = (-ws.data_ptr()) % 256
+        self.ws = ws[off: off + nbytes.value]
+        _check(lib.bcf_prepare_batch(self.c, n, int(self.precision), C.c_void_p(self.ws.data_ptr()),
+                                     nbytes.value, _stream(stream)), "bcf_prepare_batch")
+        self.out_dim = self.materials[0].out_dim
+
+    def __len__(self):
+        return len(self.materials)
+
+    def unpack(self, stream=None):
+        _check(lib.bcf_unpack_batch(self.c, len(self), C.c_void_p(self.ws.data_ptr()), _stream(stream)),
+               "bcf_unpack_batch")
+
+    @staticmethod
+    def _offsets(offsets):
+        import torch
+        if offsets.dtype != torch.int32 or not offsets.is_cuda or not offsets.is_contiguous():
+            raise TypeError("offsets must be a contiguous int32 device tensor (read as uint32)")
+        return offsets
+
+    def decode(self, queries, offsets, out=None, plan=None, stream=None):
+        """queries [n, 3] (all materials, concatenated), offsets int32 device
+        [n_materials + 1] -> out [n, out_dim]."""
+        import torch
+        q = _queries(queries)
+        offs = self._offsets(offsets)
+        if out is None:
+            out = torch.empty((q.shape[0], self.out_dim), dtype=torch.float32, device=q.device)
+        p = None if plan is None else C.byref(_BatchPlan(*plan))
+        _check(lib.bcf_decode_batch(self.c, len(self), int(self.precision), C.c_void_p(self.ws.data_ptr()),
+                                    C.c_void_p(q.data_ptr()), C.c_void_p(offs.data_ptr()), q.shape[0],
+                                    C.c_void_p(out.data_ptr()), p, _stream(stream)), "bcf_decode_batch")
+        return out
+
+    def tune(self, queries, offsets, out=None, stream=None):
+        """Times the candidate launch shapes; returns ((workgroups, interleave), ms)."""
+        import torch
+        q = _queries(queries)
+        offs = self._offsets(offsets)
+        if out is None:
+            out = torch.empty((q.shape[0], self.out_dim), dtype=torch.float32, device=q.device)
+        best = _BatchPlan()
+        ms = C.c_float(0)
+        _check(lib.bcf_tune_batch(self.c, len(self), int(self.precision), C.c_void_p(self.ws.data_ptr()),
+                                  C.c_void_p(q.data_ptr()), C.c_void_p(offs.data_ptr()), q.shape[0],
+                                  C.c_void_p(out.data_ptr()), C.byref(best), C.byref(ms), _stream(stream)),
+               "bcf_tune_batch")
+        return (best.workgroups, best.interleave), ms.value
 
 
 # ---------------------------------------------------------------------------

@@ -5,11 +5,13 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "internal.hpp"
 #include "train.hpp"
@@ -156,14 +158,13 @@ size_t elem_bytes(bcf::MlpKind k)
 // Workspace: a 256-byte header, the texel scratch (at the same offset for
 // every precision, so bcf_unpack needs none), then each layer's operands and
 // fp32 bias, and the scales.
-bcf::WsLayout layout(const bcf::MaterialDesc &d, const bcf::MlpShape &sh, bcf::MlpKind k)
+// MLP operands of precision k from byte offset `base`: each layer's operands
+// and fp32 bias, then the scales.
+bcf::WsLayout weights_layout(const bcf::MlpShape &sh, bcf::MlpKind k, size_t base)
 {
     bcf::WsLayout lay;
     std::memset(&lay, 0, sizeof lay);
-    size_t off = 256;
-    lay.scratch_off = off;
-    lay.scratch_bytes = scratch_texels(d) * 8;
-    off = align_up(off + lay.scratch_bytes, 256);
+    size_t off = base;
     lay.weights_off = off;
     const uint32_t L = sh.n_hidden + 1;
     for (uint32_t l = 0; l < L; ++l) {
@@ -176,6 +177,15 @@ bcf::WsLayout layout(const bcf::MaterialDesc &d, const bcf::MlpShape &sh, bcf::M
     off = align_up(off + 32 * sizeof(float), 256);
     lay.weights_bytes = off - lay.weights_off;
     lay.total = off;
+    return lay;
+}
+
+bcf::WsLayout layout(const bcf::MaterialDesc &d, const bcf::MlpShape &sh, bcf::MlpKind k)
+{
+    const size_t scratch_bytes = scratch_texels(d) * 8;
+    bcf::WsLayout lay = weights_layout(sh, k, align_up(256 + scratch_bytes, 256));
+    lay.scratch_off = 256;
+    lay.scratch_bytes = scratch_bytes;
     return lay;
 }
 
@@ -306,6 +316,60 @@ bcf_status bind_train_ws(bcf::TrainDesc *d, void *ws, size_t ws_bytes)
     return BCF_OK;
 }
 
+// A batch: every material valid, one MLP shape; the workspace holds a 256-byte
+// header, the material table, the item prefix, then per material its texel
+// scratch and its MLP operands.
+struct BatchLayout {
+    size_t table_off, items_off, total;
+    std::vector<bcf::BatchSlot> slots;
+    std::vector<bcf::MaterialDesc> descs;
+    bcf::MlpShape sh;
+    bcf::WsLayout rel;
+    bcf::MlpKind kind;
+};
+
+constexpr uint32_t kMaxBatch = 4096;
+
+bcf_status describe_batch(const bcf_material *mats, uint32_t n_mats, bcf_precision p, BatchLayout *b)
+{
+    if (!mats) return fail(BCF_ERR_INVALID_ARG, "materials is NULL");
+    if (n_mats < 1 || n_mats > kMaxBatch) return fail(BCF_ERR_INVALID_ARG, "n_mats = %u, expected 1..%u", n_mats, kMaxBatch);
+    if (!kind_of(p, &b->kind)) return fail(BCF_ERR_UNSUPPORTED, "precision %d not supported", (int)p);
+    if (b->kind != bcf::MLP_MFMA_F16 && b->kind != bcf::MLP_VALU_F32)
+        return fail(BCF_ERR_UNSUPPORTED, "batched decode runs BCF_FP16 or BCF_FP32");
+    b->descs.resize(n_mats);
+    b->slots.resize(n_mats);
+    size_t off = 256;
+    b->table_off = off;
+    off = align_up(off + bcf::batch_table_bytes(n_mats), 256);
+    b->items_off = off;
+    off = align_up(off + (size_t)(n_mats + 1) * 4, 256);
+    for (uint32_t k = 0; k < n_mats; ++k) {
+        bcf::MlpShape sh;
+        const bcf_status st = describe(&mats[k], &b->descs[k], &sh);
+        if (st != BCF_OK) {
+            const std::string why = g_error;
+            return fail(st, "material %u: %s", k, why.c_str());
+        }
+        if (k == 0) {
+            b->sh = sh;
+        } else if (sh.n_layers != b->sh.n_layers ||
+                   std::memcmp(sh.dims, b->sh.dims, sizeof(uint32_t) * (sh.n_layers + 1)) != 0) {
+            return fail(BCF_ERR_INVALID_ARG, "material %u: MLP dims differ from material 0", k);
+        }
+        b->slots[k].scratch_off = off;
+        b->slots[k].scratch_bytes = scratch_texels(b->descs[k]) * 8;
+        off = align_up(off + b->slots[k].scratch_bytes, 256);
+    }
+    b->rel = weights_layout(b->sh, b->kind, 0);
+    for (uint32_t k = 0; k < n_mats; ++k) {
+        b->slots[k].weights_off = off;
+        off += b->rel.weights_bytes;
+    }
+    b->total = off;
+    return BCF_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -354,14 +418,14 @@ bcf_status bcf_decode(const bcf_material *m, bcf_precision p, void *ws, const fl
     bcf::MaterialDesc d;
     bcf::MlpShape sh;
     bcf::MlpKind kind;
-    (void)grid_width;
     bcf_status st = decode_args(m, p, ws, queries, n, out, &d, &sh, &kind);
     if (st != BCF_OK || n == 0) return st;
     const bcf::WsLayout lay = layout(d, sh, kind);
     hipStream_t s = static_cast<hipStream_t>(stream);
     st = unpack(d, lay, ws, s);
     if (st != BCF_OK) return st;
-    return device_status(bcf::launch_filter_mlp(d, sh, kind, lay, ws, queries, n, out, s), "decode launch");
+    return device_status(bcf::launch_filter_mlp(d, sh, kind, lay, ws, queries, n, grid_width, out, s),
+                         "decode launch");
 }
 
 bcf_status bcf_unpack(const bcf_material *m, void *ws, void *stream)
@@ -382,11 +446,11 @@ bcf_status bcf_decode_unpacked(const bcf_material *m, bcf_precision p, const voi
     bcf::MaterialDesc d;
     bcf::MlpShape sh;
     bcf::MlpKind kind;
-    (void)grid_width;
     bcf_status st = decode_args(m, p, ws, queries, n, out, &d, &sh, &kind);
     if (st != BCF_OK || n == 0) return st;
     const bcf::WsLayout lay = layout(d, sh, kind);
-    return device_status(bcf::launch_filter_mlp(d, sh, kind, lay, ws, queries, n, out, static_cast<hipStream_t>(stream)),
+    return device_status(bcf::launch_filter_mlp(d, sh, kind, lay, ws, queries, n, grid_width, out,
+                                                static_cast<hipStream_t>(stream)),
                          "decode launch");
 }
 
@@ -466,6 +530,135 @@ bcf_status bcf_train_backward(const bcf_train_material *m, void *ws, const float
     d.g_params = grad_params;
     return device_status(bcf::launch_train_backward(d, queries, n, grad_out, static_cast<hipStream_t>(stream)),
                          "train backward launch");
+}
+
+bcf_status bcf_batch_workspace_size(const bcf_material *mats, uint32_t n_mats, bcf_precision p, size_t *ws_bytes)
+{
+    if (!ws_bytes) return fail(BCF_ERR_INVALID_ARG, "ws_bytes is NULL");
+    BatchLayout b;
+    const bcf_status st = describe_batch(mats, n_mats, p, &b);
+    if (st == BCF_OK) *ws_bytes = b.total;
+    return st;
+}
+
+bcf_status bcf_prepare_batch(const bcf_material *mats, uint32_t n_mats, bcf_precision p, void *ws, size_t ws_bytes,
+                             void *stream)
+{
+    BatchLayout b;
+    bcf_status st = describe_batch(mats, n_mats, p, &b);
+    if (st != BCF_OK) return st;
+    if (!ws || !aligned(ws, 256)) return fail(BCF_ERR_INVALID_ARG, "workspace NULL or not 256-byte aligned");
+    if (ws_bytes < b.total) return fail(BCF_ERR_INVALID_ARG, "workspace of %zu bytes, need %zu", ws_bytes, b.total);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (uint32_t k = 0; k < n_mats; ++k) {
+        st = device_status(bcf::launch_prepare_weights(mats[k].params, nullptr, b.sh, b.kind, b.rel,
+                                                       static_cast<uint8_t *>(ws) + b.slots[k].weights_off, s),
+                           "prepare launch");
+        if (st != BCF_OK) return st;
+    }
+    return device_status(bcf::write_batch_table(b.descs.data(), b.slots.data(), n_mats, b.sh.out, ws, b.table_off, s),
+                         "material table copy");
+}
+
+bcf_status bcf_unpack_batch(const bcf_material *mats, uint32_t n_mats, void *ws, void *stream)
+{
+    BatchLayout b;
+    bcf_status st = describe_batch(mats, n_mats, BCF_FP16, &b);
+    if (st != BCF_OK) return st;
+    if (!ws || !aligned(ws, 256)) return fail(BCF_ERR_INVALID_ARG, "workspace NULL or not 256-byte aligned");
+    for (uint32_t k = 0; k < n_mats; ++k) {
+        uint2 *texels = reinterpret_cast<uint2 *>(static_cast<uint8_t *>(ws) + b.slots[k].scratch_off);
+        st = device_status(bcf::launch_predecode(b.descs[k], predecode_plan(b.descs[k]), texels,
+                                                 static_cast<hipStream_t>(stream)),
+                           "unpack launch");
+        if (st != BCF_OK) return st;
+    }
+    return BCF_OK;
+}
+
+namespace {
+
+bcf_status batch_args(const bcf_material *mats, uint32_t n_mats, bcf_precision p, void *ws, const float *queries,
+                      const uint32_t *offsets, uint32_t n_total, float *out, BatchLayout *b)
+{
+    const bcf_status st = describe_batch(mats, n_mats, p, b);
+    if (st != BCF_OK) return st;
+    if (!ws || !aligned(ws, 256)) return fail(BCF_ERR_INVALID_ARG, "workspace NULL or not 256-byte aligned");
+    if (!offsets || !aligned(offsets, 4)) return fail(BCF_ERR_INVALID_ARG, "offsets NULL or misaligned");
+    if (n_total > 0 && (!queries || !aligned(queries, 4) || !out || !aligned(out, 4)))
+        return fail(BCF_ERR_INVALID_ARG, "queries or out NULL or misaligned");
+    return BCF_OK;
+}
+
+unsigned default_workgroups(uint32_t n_total)
+{
+    const uint64_t items = ((uint64_t)n_total + 63) / 64;
+    return (unsigned)std::min<uint64_t>(std::max<uint64_t>((items + 3) / 4, 8), 2048);
+}
+
+}  // namespace
+
+bcf_status bcf_decode_batch(const bcf_material *mats, uint32_t n_mats, bcf_precision p, void *ws,
+                            const float *queries, const uint32_t *offsets, uint32_t n_total, float *out,
+                            const bcf_batch_plan *plan, void *stream)
+{
+    BatchLayout b;
+    const bcf_status st = batch_args(mats, n_mats, p, ws, queries, offsets, n_total, out, &b);
+    if (st != BCF_OK) return st;
+    const unsigned wg = plan && plan->workgroups ? plan->workgroups : default_workgroups(n_total);
+    const uint32_t inter = plan ? (plan->interleave ? 1u : 0u) : 1u;
+    return device_status(bcf::launch_batch(ws, b.table_off, b.items_off, b.rel, b.sh, b.kind, queries, offsets, n_mats,
+                                           n_total, out, wg, inter, static_cast<hipStream_t>(stream)),
+                         "batch launch");
+}
+
+bcf_status bcf_tune_batch(const bcf_material *mats, uint32_t n_mats, bcf_precision p, void *ws,
+                          const float *queries, const uint32_t *offsets, uint32_t n_total, float *out,
+                          bcf_batch_plan *best, float *best_ms, void *stream)
+{
+    BatchLayout b;
+    bcf_status st = batch_args(mats, n_mats, p, ws, queries, offsets, n_total, out, &b);
+    if (st != BCF_OK) return st;
+    if (!best) return fail(BCF_ERR_INVALID_ARG, "best is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipEvent_t e0, e1;
+    if ((st = device_status(hipEventCreate(&e0), "event")) != BCF_OK) return st;
+    if ((st = device_status(hipEventCreate(&e1), "event")) != BCF_OK) {
+        (void)hipEventDestroy(e0);
+        return st;
+    }
+    static const unsigned kGroups[] = {256, 512, 1024, 2048, 4096};
+    float best_t = -1.0f;
+    bcf_batch_plan pick = {default_workgroups(n_total), 1};
+    for (unsigned wg : kGroups) {
+        for (uint32_t inter = 0; inter < 2 && st == BCF_OK; ++inter) {
+            auto run = [&]() {
+                return device_status(bcf::launch_batch(ws, b.table_off, b.items_off, b.rel, b.sh, b.kind, queries,
+                                                       offsets, n_mats, n_total, out, wg, inter, s),
+                                     "batch launch");
+            };
+            if ((st = run()) != BCF_OK) break;                       // warm-up
+            (void)hipEventRecord(e0, s);
+            for (int r = 0; r < 3 && st == BCF_OK; ++r) st = run();
+            (void)hipEventRecord(e1, s);
+            if (st != BCF_OK || (st = device_status(hipEventSynchronize(e1), "tune sync")) != BCF_OK) break;
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            ms /= 3.0f;
+            if (best_t < 0.0f || ms < best_t) {
+                best_t = ms;
+                pick.workgroups = wg;
+                pick.interleave = inter;
+            }
+        }
+        if (st != BCF_OK) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != BCF_OK) return st;
+    *best = pick;
+    if (best_ms) *best_ms = best_t;
+    return BCF_OK;
 }
 
 }  // extern "C"

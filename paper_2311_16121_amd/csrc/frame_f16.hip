@@ -9,4 +9,9 @@ hipError_t launch_frame_f16(const FrameArgs &a, const MlpShape &sh, bool shared,
                   : launch_frame_kind<MLP_MFMA_F16, 16, false>(a, sh, grid, s);
 }
 
+hipError_t launch_batch_f16(const BatchArgs &a, const MlpShape &sh, unsigned grid, hipStream_t s)
+{
+    return launch_batch_kind<MLP_MFMA_F16, 16>(a, sh, grid, s);
+}
+
 }  // namespace bcf

@@ -37,7 +37,29 @@ struct FrameArgs {
     uint32_t n;                            // queries of this launch
     uint32_t out_dim;
     float *absmax;                         // k_calibrate: per-layer largest |input|
+    // 2D work items: with grid_w > 0 the queries are image rows of grid_w and
+    // a wave takes an 8x8 tile (lane = 8 row + column); with 0, 64 consecutive
+    // queries. rows_b128: grid_w * out_dim is a multiple of 4 (16-byte rows)
+    uint32_t grid_w, tiles_x, n_items, rows_b128;
 };
+
+// Workgroups are dispatched to the 8 XCDs round-robin (workgroup b runs on XCD
+// b % 8), each XCD with its own L2. The workgroups of one XCD take a
+// contiguous band of the work items, so neighbouring items -- which read
+// overlapping texels -- share that L2. The grid is a multiple of 8.
+constexpr uint32_t kXcds = 8;
+
+struct ItemRange {
+    uint32_t first, end, step;
+};
+
+__device__ __forceinline__ ItemRange wave_items(uint32_t n_items, uint32_t wv)
+{
+    const uint32_t xcd = blockIdx.x % kXcds, local = blockIdx.x / kXcds;
+    const uint32_t lo = (uint32_t)((uint64_t)n_items * xcd / kXcds);
+    const uint32_t hi = (uint32_t)((uint64_t)n_items * (xcd + 1) / kXcds);
+    return ItemRange{lo + local * kFrameWaves + wv, hi, (gridDim.x / kXcds) * kFrameWaves};
+}
 
 struct Query {
     float u, v, s;
@@ -62,10 +84,11 @@ __device__ __forceinline__ const_float *constant_floats(const uint8_t *p)
 }
 
 template <int H, int NH, int C>
-__device__ __forceinline__ void mlp_valu(const FrameArgs &a, const float z[12], float o[C], float *amax)
+__device__ __forceinline__ void mlp_valu(const uint8_t *ws, const WsLayout &lay, const float z[12], float o[C],
+                                         float *amax)
 {
-    const_float *W = constant_floats(a.ws + a.lay.layer_w_off[0]);
-    const_float *B = constant_floats(a.ws + a.lay.layer_b_off[0]);
+    const_float *W = constant_floats(ws + lay.layer_w_off[0]);
+    const_float *B = constant_floats(ws + lay.layer_b_off[0]);
     if (amax) {
 #pragma unroll
         for (int i = 0; i < 12; ++i) amax[0] = fmaxf(amax[0], fabsf(z[i]));
@@ -84,8 +107,8 @@ __device__ __forceinline__ void mlp_valu(const FrameArgs &a, const float z[12], 
 #pragma unroll
             for (int i = 0; i < H; ++i) amax[l] = fmaxf(amax[l], hcur[i]);
         }
-        W = constant_floats(a.ws + a.lay.layer_w_off[l]);
-        B = constant_floats(a.ws + a.lay.layer_b_off[l]);
+        W = constant_floats(ws + lay.layer_w_off[l]);
+        B = constant_floats(ws + lay.layer_b_off[l]);
         float hn[H];
 #pragma unroll
         for (int j = 0; j < H; ++j) {
@@ -101,8 +124,8 @@ __device__ __forceinline__ void mlp_valu(const FrameArgs &a, const float z[12], 
 #pragma unroll
         for (int i = 0; i < H; ++i) amax[NH] = fmaxf(amax[NH], hcur[i]);
     }
-    W = constant_floats(a.ws + a.lay.layer_w_off[NH]);
-    B = constant_floats(a.ws + a.lay.layer_b_off[NH]);
+    W = constant_floats(ws + lay.layer_w_off[NH]);
+    B = constant_floats(ws + lay.layer_b_off[NH]);
 #pragma unroll
     for (int j = 0; j < C; ++j) {
         float acc = B[j];
@@ -127,6 +150,65 @@ __device__ __forceinline__ void copy_lut(const LevelLut &src, LevelLut &dst)
     __syncthreads();
 }
 
+// One wave's 64 queries: filter (eqs. 9, 10), concatenate, MLP (eq. 3); the
+// outputs land in the wave's LDS stage, lane L's at st[L * out_dim ...].
+template <MlpKind K, int H, int NH, int C, bool SHARED>
+__device__ __forceinline__ void decode_wave(const Query &qq, __amdgpu_buffer_rsrc_t rs, const LevelLut &lut,
+                                            const float *levels_bias, uint32_t stride, const uint8_t *wbase,
+                                            const WsLayout &lay,
+                                            const MfmaMlp<K == MLP_VALU_F32 ? MLP_MFMA_F16 : K, H, NH> &mlp,
+                                            float4_t (*feats)[4], float *st, uint32_t out_dim, uint32_t lane)
+{
+    constexpr bool VALU = K == MLP_VALU_F32;
+    const uint32_t g = lane >> 4, qi = lane & 15;
+    float z[12];
+    filter4<SHARED>(rs, lut, levels_bias, stride, qq.u, qq.v, qq.s, z);
+    if (VALU) {
+        float o[C];
+        mlp_valu<H, NH, C>(wbase, lay, z, o, nullptr);
+#pragma unroll
+        for (int j = 0; j < C; ++j)
+            if ((uint32_t)j < out_dim) st[lane * out_dim + j] = o[j];
+    } else {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const float4_t v4 = {z[3 * t], z[3 * t + 1], z[3 * t + 2], 0.0f};
+            feats[lane][t] = v4;
+        }
+        wave_lds_sync();
+#pragma unroll
+        for (int grp = 0; grp < 4; ++grp) {
+            const float4_t f4 = feats[16 * grp + qi][g];
+            const float f[4] = {f4[0], f4[1], f4[2], f4[3]};
+            const float4_t o4 = mlp.run(f);
+            const uint32_t row = (16 * grp + qi) * out_dim;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (4 * g + j < out_dim) st[row + 4 * g + j] = o4[j];
+        }
+    }
+    wave_lds_sync();
+}
+
+// Item `it` of a run of n consecutive queries: its (up to) 64 staged rows go
+// to out as 16-byte stores, the last partial item as 4-byte stores.
+__device__ __forceinline__ void store_run(const float4_t *stage, __amdgpu_buffer_rsrc_t ro, uint32_t it, uint32_t n,
+                                          uint32_t out_dim, uint32_t lane)
+{
+    const uint32_t base = it * 64u * out_dim * 4u;
+    if (it * 64 + 64 <= n) {
+        for (uint32_t k = lane; k < 16 * out_dim; k += 64)
+            __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(uint4_t, stage[k]), ro, (int)(base + 16u * k),
+                                                   0, 0);
+    } else {
+        const float *st = reinterpret_cast<const float *>(stage);
+        const uint32_t floats = (n - it * 64) * out_dim;
+        for (uint32_t k = lane; k < floats; k += 64)
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, st[k]), ro, (int)(base + 4u * k), 0,
+                                                  0);
+    }
+}
+
 template <MlpKind K, int H, int NH, int C, bool SHARED>
 __global__ void __launch_bounds__(kFrameThreads) k_frame(FrameArgs a)
 {
@@ -143,53 +225,49 @@ __global__ void __launch_bounds__(kFrameThreads) k_frame(FrameArgs a)
     MfmaMlp<VALU ? MLP_MFMA_F16 : K, H, NH> mlp;
     if (!VALU) mlp.load(a.ws, a.lay, lane);
     float *st = reinterpret_cast<float *>(&stage[wv][0]);
-    const uint32_t g = lane >> 4, qi = lane & 15;
 
-    const uint32_t n_iter = (a.n + 63) / 64;
-    const uint32_t n_waves = gridDim.x * kFrameWaves;
-    for (uint32_t it = blockIdx.x * kFrameWaves + wv; it < n_iter; it += n_waves) {
-        const uint32_t q = it * 64 + lane;
-        // queries past n read as zeros (buffer range check); their rows are not stored
-        const Query qq = load_query(rq, q);
-        float z[12];
-        filter4<SHARED>(rs, lut, a.levels_bias, a.stride, qq.u, qq.v, qq.s, z);
-        if (VALU) {
-            float o[C];
-            mlp_valu<H, NH, C>(a, z, o, nullptr);
-#pragma unroll
-            for (int j = 0; j < C; ++j)
-                if ((uint32_t)j < a.out_dim) st[lane * a.out_dim + j] = o[j];
+    const ItemRange items = wave_items(a.n_items, wv);
+    for (uint32_t it = items.first; it < items.end; it += items.step) {
+        // this lane's query; lanes outside the image or past n read zeros
+        // (buffer range check) and their rows are not stored
+        uint32_t q, row0 = 0, col0 = 0;
+        if (a.grid_w) {
+            row0 = (it / a.tiles_x) * 8u;
+            col0 = (it % a.tiles_x) * 8u;
+            const uint32_t col = col0 + (lane & 7u);
+            q = (row0 + (lane >> 3)) * a.grid_w + col;
+            q = col < a.grid_w && q < a.n ? q : a.n;
         } else {
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const float4_t v4 = {z[3 * t], z[3 * t + 1], z[3 * t + 2], 0.0f};
-                feats[wv][lane][t] = v4;
-            }
-            wave_lds_sync();
-#pragma unroll
-            for (int grp = 0; grp < 4; ++grp) {
-                const float4_t f4 = feats[wv][16 * grp + qi][g];
-                const float f[4] = {f4[0], f4[1], f4[2], f4[3]};
-                const float4_t o4 = mlp.run(f);
-                const uint32_t row = (16 * grp + qi) * a.out_dim;
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    if (4 * g + j < a.out_dim) st[row + 4 * g + j] = o4[j];
-            }
+            q = it * 64 + lane;
         }
-        wave_lds_sync();
-        // the wave's rows are 64 * out_dim contiguous floats (a multiple of 16 bytes)
-        const uint32_t base = it * 64u * a.out_dim * 4u;
-        if (it * 64 + 64 <= a.n) {
-            const uint32_t chunks = 16 * a.out_dim;
-            for (uint32_t k = lane; k < chunks; k += 64)
-                __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(uint4_t, stage[wv][k]), ro,
-                                                       (int)(base + 16u * k), 0, 0);
-        } else {                                       // last, partial iteration
-            const uint32_t floats = (a.n - it * 64) * a.out_dim;
-            for (uint32_t k = lane; k < floats; k += 64)
-                __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, st[k]), ro,
-                                                      (int)(base + 4u * k), 0, 0);
+        const Query qq = load_query(rq, q);
+        decode_wave<K, H, NH, C, SHARED>(qq, rs, lut, a.levels_bias, a.stride, a.ws, a.lay, mlp, feats[VALU ? 0 : wv],
+                                         st, a.out_dim, lane);
+        // Staged rows: lane L's outputs at st[L * out_dim ...]. A run of 8 (tile
+        // row) or 64 (consecutive queries) lanes is one contiguous span of out.
+        const uint32_t chunks = 16 * a.out_dim;          // 64 rows of out_dim floats in 16 bytes
+        if (!a.grid_w) {
+            store_run(stage[wv], ro, it, a.n, a.out_dim, lane);
+        } else {
+            const bool full = col0 + 8u <= a.grid_w && (row0 + 7u) * a.grid_w + col0 + 8u <= a.n;
+            if (full && a.rows_b128) {
+                const uint32_t per_row = 2u * a.out_dim;     // 8 rows of out_dim floats in 16 bytes
+                for (uint32_t k = lane; k < chunks; k += 64) {
+                    const uint32_t r = k / per_row, c = k - r * per_row;
+                    const uint32_t off = ((row0 + r) * a.grid_w + col0) * a.out_dim * 4u + 16u * c;
+                    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(uint4_t, stage[wv][k]), ro, (int)off,
+                                                           0, 0);
+                }
+            } else {                                   // an edge tile
+                for (uint32_t k = lane; k < 64u * a.out_dim; k += 64) {
+                    const uint32_t src = k / a.out_dim, j = k - src * a.out_dim;
+                    const uint32_t col = col0 + (src & 7u);
+                    const uint32_t qq2 = (row0 + (src >> 3)) * a.grid_w + col;
+                    if (col < a.grid_w && qq2 < a.n)
+                        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, st[k]), ro,
+                                                              (int)((qq2 * a.out_dim + j) * 4u), 0, 0);
+                }
+            }
         }
         wave_lds_sync();
     }
@@ -211,7 +289,7 @@ __global__ void __launch_bounds__(kFrameThreads) k_calibrate(FrameArgs a)
         const Query qq = load_query(rq, q);
         float z[12], o[C];
         filter4<SHARED>(rs, lut, a.levels_bias, a.stride, qq.u, qq.v, qq.s, z);
-        mlp_valu<H, NH, C>(a, z, o, amax);
+        mlp_valu<H, NH, C>(a.ws, a.lay, z, o, amax);
     }
 #pragma unroll
     for (int l = 0; l <= NH; ++l) {
@@ -221,6 +299,125 @@ __global__ void __launch_bounds__(kFrameThreads) k_calibrate(FrameArgs a)
 }
 
 
+
+
+// ---------------------------------------------------------------------------
+// Many materials in one launch. Every material has its own pyramids, texel
+// scratch and MLP weights (one MLP shape for all); its queries are a
+// contiguous range of the concatenated query array. Work items are runs of 64
+// queries of one material, numbered material after material.
+
+struct BatchMat {
+    LevelLut lut;                          // as FrameArgs, offsets within the material's scratch
+    float levels_bias[2 * kMaxTextures];
+    uint64_t scratch_off, weights_off;     // bytes from the workspace start
+    uint32_t scratch_bytes, stride, shared, pad;
+};
+
+struct BatchArgs {
+    const uint8_t *ws;
+    const BatchMat *mats;                  // [n_mats], in the workspace
+    const uint32_t *offsets;               // caller's [n_mats + 1] first query of each material
+    uint32_t *items;                       // [n_mats + 1] first item of each material (k_batch_items)
+    WsLayout lay;                          // weight layout relative to a material's weights_off
+    const float *queries;
+    float *out;
+    uint32_t n_mats, n_total, out_dim;
+    uint32_t interleave;                   // 1: waves of an XCD interleave items; 0: contiguous ranges
+};
+
+// Query range of material k: the caller's offsets clamped to [0, n_total],
+// made non-decreasing, at most kMaxQueriesPerLaunch queries.
+__device__ __forceinline__ void batch_range(const BatchArgs &a, uint32_t k, uint32_t &q0, uint32_t &cnt)
+{
+    q0 = min(a.offsets[k], a.n_total);
+    const uint32_t q1 = max(min(a.offsets[k + 1], a.n_total), q0);
+    cnt = min(q1 - q0, (uint32_t)kMaxQueriesPerLaunch);
+}
+
+template <MlpKind K, int H, int NH, int C>
+__global__ void __launch_bounds__(kFrameThreads) k_batch(BatchArgs a)
+{
+    constexpr bool VALU = K == MLP_VALU_F32;
+    __shared__ LevelLut lut[kFrameWaves];                 // each wave's current material
+    __shared__ float4_t feats[VALU ? 1 : kFrameWaves][64][4];
+    __shared__ float4_t stage[kFrameWaves][64 * kMaxOut / 4];
+    const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    float *st = reinterpret_cast<float *>(&stage[wv][0]);
+    const uint32_t total = a.items[a.n_mats];
+
+    ItemRange items;
+    if (a.interleave) {
+        items = wave_items(total, wv);
+    } else {
+        // contiguous: the XCD's band split into one range per wave
+        const uint32_t xcd = blockIdx.x % kXcds, local = blockIdx.x / kXcds;
+        const uint32_t waves = (gridDim.x / kXcds) * kFrameWaves, w = local * kFrameWaves + wv;
+        const uint64_t lo = (uint64_t)total * xcd / kXcds, hi = (uint64_t)total * (xcd + 1) / kXcds;
+        items.first = (uint32_t)(lo + (hi - lo) * w / waves);
+        items.end = (uint32_t)(lo + (hi - lo) * (w + 1) / waves);
+        items.step = 1;
+    }
+
+    MfmaMlp<VALU ? MLP_MFMA_F16 : K, H, NH> mlp;
+    uint32_t cur = 0xFFFFFFFFu, first_item = 0, n_k = 0, shared = 0, stride = 0;
+    float lb[2 * kMaxTextures];
+    const uint8_t *wbase = a.ws;
+    __amdgpu_buffer_rsrc_t rs = make_rsrc(a.ws, 0), rq = rs, ro = rs;
+    for (uint32_t it = items.first; it < items.end; it += items.step) {
+        // the material: the last k with items[k] <= it (empty materials share
+        // their first item with the next one, which the search lands on)
+        uint32_t lo = 0, hi = a.n_mats;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (a.items[mid] <= it) lo = mid;
+            else hi = mid;
+        }
+        if (lo != cur) {
+            cur = lo;
+            const BatchMat &M = a.mats[cur];
+            lut[wv].e[lane >> 4][lane & 15] = M.lut.e[lane >> 4][lane & 15];
+#pragma unroll
+            for (int j = 0; j < 2 * kMaxTextures; ++j) lb[j] = M.levels_bias[j];
+            shared = M.shared;
+            stride = M.stride;
+            rs = make_rsrc(a.ws + M.scratch_off, M.scratch_bytes);
+            uint32_t q0;
+            batch_range(a, cur, q0, n_k);
+            rq = make_rsrc(a.queries + 3ull * q0, n_k * 12u);
+            ro = make_rsrc(a.out + (uint64_t)a.out_dim * q0, n_k * a.out_dim * 4u);
+            wbase = a.ws + M.weights_off;
+            if (!VALU) mlp.load(wbase, a.lay, lane);
+            first_item = a.items[cur];
+            wave_lds_sync();
+        }
+        const uint32_t j = it - first_item;
+        const Query qq = load_query(rq, j * 64 + lane);   // past n_k: zeros, not stored
+        if (shared)
+            decode_wave<K, H, NH, C, true>(qq, rs, lut[wv], lb, stride, wbase, a.lay, mlp, feats[VALU ? 0 : wv], st,
+                                           a.out_dim, lane);
+        else
+            decode_wave<K, H, NH, C, false>(qq, rs, lut[wv], lb, stride, wbase, a.lay, mlp, feats[VALU ? 0 : wv], st,
+                                            a.out_dim, lane);
+        store_run(stage[wv], ro, j, n_k, a.out_dim, lane);
+        wave_lds_sync();
+    }
+}
+
+template <MlpKind K, int C>
+hipError_t launch_batch_kind(const BatchArgs &a, const MlpShape &sh, unsigned grid, hipStream_t s)
+{
+#define BCF_CASE(H, NH)                                                                       \
+    if (sh.hidden == H && sh.n_hidden == NH) {                                               \
+        k_batch<K, H, NH, C><<<grid, kFrameThreads, 0, s>>>(a);                               \
+        return hipGetLastError();                                                             \
+    }
+    BCF_CASE(16, 1) BCF_CASE(16, 2) BCF_CASE(16, 3)
+    BCF_CASE(32, 1) BCF_CASE(32, 2) BCF_CASE(32, 3)
+    BCF_CASE(64, 1) BCF_CASE(64, 2) BCF_CASE(64, 3)
+#undef BCF_CASE
+    return hipErrorInvalidValue;
+}
 
 template <MlpKind K, int C, bool SH>
 hipError_t launch_frame_kind(const FrameArgs &a, const MlpShape &sh, unsigned grid, hipStream_t s)
@@ -246,5 +443,7 @@ hipError_t launch_frame_f32_mfma(const FrameArgs &a, const MlpShape &sh, bool sh
                                  hipStream_t s);
 hipError_t launch_calibrate_kernel(const FrameArgs &a, const MlpShape &sh, bool shared, unsigned grid,
                                    hipStream_t s);
+hipError_t launch_batch_f16(const BatchArgs &a, const MlpShape &sh, unsigned grid, hipStream_t s);
+hipError_t launch_batch_f32(const BatchArgs &a, const MlpShape &sh, unsigned grid, hipStream_t s);
 
 }  // namespace bcf

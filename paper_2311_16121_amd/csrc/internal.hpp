@@ -77,8 +77,25 @@ hipError_t launch_prepare_weights(const float *params, const float *act_absmax, 
 hipError_t launch_calibrate(const MaterialDesc &m, const MlpShape &sh, const WsLayout &lay, const void *ws,
                             const float *queries, size_t n, float *absmax, hipStream_t s);
 
+// grid_width >= 8: the queries are an image of that many columns (row-major);
+// results do not depend on it
 hipError_t launch_filter_mlp(const MaterialDesc &m, const MlpShape &sh, MlpKind kind,
                              const WsLayout &lay, const void *ws, const float *queries, size_t n,
-                             float *out, hipStream_t s);
+                             uint32_t grid_width, float *out, hipStream_t s);
+
+// Many materials: where each material's texel scratch and MLP weights sit in
+// the batch workspace.
+struct BatchSlot {
+    size_t scratch_off, scratch_bytes, weights_off;
+};
+
+size_t batch_table_bytes(uint32_t n_mats);
+// builds the per-material table and copies it into the workspace (synchronises s)
+hipError_t write_batch_table(const MaterialDesc *mats, const BatchSlot *slots, uint32_t n_mats, uint32_t out_dim,
+                             void *ws, size_t table_off, hipStream_t s);
+// rel: the weight layout relative to a material's weights_off
+hipError_t launch_batch(void *ws, size_t table_off, size_t items_off, const WsLayout &rel, const MlpShape &sh,
+                        MlpKind kind, const float *queries, const uint32_t *offsets, uint32_t n_mats,
+                        uint32_t n_total, float *out, unsigned workgroups, uint32_t interleave, hipStream_t s);
 
 }  // namespace bcf

@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <vector>
 
 #include "bc6h_device.hpp"
 #include "frame_kernels.hpp"
@@ -345,37 +346,126 @@ static FrameArgs frame_args(const MaterialDesc &m, const WsLayout &lay, const vo
     return a;
 }
 
-static unsigned frame_grid(uint32_t n)
+// Persistent waves: at most 16 workgroups of 4 waves per CU, a multiple of the XCD count.
+static unsigned frame_grid(uint32_t items)
 {
-    const uint32_t iters = (n + 63) / 64;
-    return std::max(1u, std::min<uint32_t>((iters + kFrameWaves - 1) / kFrameWaves, 256u * 16u));
+    const uint32_t blocks = std::min<uint32_t>((items + kFrameWaves - 1) / kFrameWaves, 256u * 16u);
+    return std::max(kXcds, (blocks + kXcds - 1) / kXcds * kXcds);
 }
 
 hipError_t launch_filter_mlp(const MaterialDesc &m, const MlpShape &sh, MlpKind kind,
                              const WsLayout &lay, const void *ws, const float *queries, size_t n,
-                             float *out, hipStream_t s)
+                             uint32_t grid_width, float *out, hipStream_t s)
 {
     bool shared;
     FrameArgs a = frame_args(m, lay, ws, sh.out, &shared);
+    auto launch = [&](unsigned grid) -> hipError_t {
+        switch (kind) {
+        case MLP_VALU_F32: return launch_frame_f32(a, sh, shared, grid, s);
+        case MLP_MFMA_F16: return launch_frame_f16(a, sh, shared, grid, s);
+        case MLP_MFMA_BF16: return launch_frame_bf16(a, sh, shared, grid, s);
+        case MLP_MFMA_FP8: return launch_frame_fp8(a, sh, shared, grid, s);
+        case MLP_MFMA_F32: return launch_frame_f32_mfma(a, sh, shared, grid, s);
+        default: return hipErrorInvalidValue;
+        }
+    };
+    if (grid_width >= 8 && grid_width <= n && n <= kMaxQueriesPerLaunch) {
+        // an image of grid_width columns: 8x8 tiles, so a wave's queries read
+        // overlapping texels in both directions
+        const uint32_t rows = (uint32_t)((n + grid_width - 1) / grid_width);
+        a.queries = queries;
+        a.out = out;
+        a.n = (uint32_t)n;
+        a.grid_w = grid_width;
+        a.tiles_x = (grid_width + 7) / 8;
+        a.n_items = a.tiles_x * ((rows + 7) / 8);
+        a.rows_b128 = (grid_width * sh.out) % 4 == 0;
+        return launch(frame_grid(a.n_items));
+    }
     // one launch covers at most kMaxQueriesPerLaunch queries (32-bit buffer offsets)
     for (size_t first = 0; first < n; first += kMaxQueriesPerLaunch) {
         const uint32_t cnt = (uint32_t)std::min<size_t>(n - first, kMaxQueriesPerLaunch);
         a.queries = queries + 3 * first;
         a.out = out + sh.out * first;
         a.n = cnt;
-        const unsigned grid = frame_grid(cnt);
-        hipError_t e;
-        switch (kind) {
-        case MLP_VALU_F32: e = launch_frame_f32(a, sh, shared, grid, s); break;
-        case MLP_MFMA_F16: e = launch_frame_f16(a, sh, shared, grid, s); break;
-        case MLP_MFMA_BF16: e = launch_frame_bf16(a, sh, shared, grid, s); break;
-        case MLP_MFMA_FP8: e = launch_frame_fp8(a, sh, shared, grid, s); break;
-        case MLP_MFMA_F32: e = launch_frame_f32_mfma(a, sh, shared, grid, s); break;
-        default: e = hipErrorInvalidValue;
-        }
+        a.n_items = (cnt + 63) / 64;
+        const hipError_t e = launch(frame_grid(a.n_items));
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
+// many materials
+
+size_t batch_table_bytes(uint32_t n_mats) { return sizeof(BatchMat) * n_mats; }
+
+// First work item of every material (runs of 64 queries), one lane.
+__global__ void k_batch_items(BatchArgs a)
+{
+    if (threadIdx.x != 0) return;
+    uint32_t acc = 0;
+    for (uint32_t k = 0; k < a.n_mats; ++k) {
+        a.items[k] = acc;
+        uint32_t q0, cnt;
+        batch_range(a, k, q0, cnt);
+        acc += (cnt + 63u) / 64u;
+    }
+    a.items[a.n_mats] = acc;
+}
+
+hipError_t write_batch_table(const MaterialDesc *mats, const BatchSlot *slots, uint32_t n_mats, uint32_t out_dim,
+                             void *ws, size_t table_off, hipStream_t s)
+{
+    std::vector<BatchMat> table(n_mats);
+    for (uint32_t k = 0; k < n_mats; ++k) {
+        WsLayout lay;
+        std::memset(&lay, 0, sizeof lay);
+        lay.scratch_off = slots[k].scratch_off;
+        bool shared;
+        const FrameArgs a = frame_args(mats[k], lay, ws, out_dim, &shared);
+        BatchMat &b = table[k];
+        std::memset(&b, 0, sizeof b);
+        b.lut = a.lut;
+        std::memcpy(b.levels_bias, a.levels_bias, sizeof b.levels_bias);
+        b.scratch_off = slots[k].scratch_off;
+        b.weights_off = slots[k].weights_off;
+        b.scratch_bytes = (uint32_t)slots[k].scratch_bytes;
+        b.stride = a.stride;
+        b.shared = shared ? 1u : 0u;
+    }
+    hipError_t e = hipMemcpyAsync(static_cast<uint8_t *>(ws) + table_off, table.data(), sizeof(BatchMat) * n_mats,
+                                  hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(s);           // the host table goes out of scope
+}
+
+hipError_t launch_batch(void *ws, size_t table_off, size_t items_off, const WsLayout &rel, const MlpShape &sh,
+                        MlpKind kind, const float *queries, const uint32_t *offsets, uint32_t n_mats,
+                        uint32_t n_total, float *out, unsigned workgroups, uint32_t interleave, hipStream_t s)
+{
+    BatchArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.ws = static_cast<const uint8_t *>(ws);
+    a.mats = reinterpret_cast<const BatchMat *>(static_cast<uint8_t *>(ws) + table_off);
+    a.offsets = offsets;
+    a.items = reinterpret_cast<uint32_t *>(static_cast<uint8_t *>(ws) + items_off);
+    a.lay = rel;
+    a.queries = queries;
+    a.out = out;
+    a.n_mats = n_mats;
+    a.n_total = n_total;
+    a.out_dim = sh.out;
+    a.interleave = interleave;
+    k_batch_items<<<1, 64, 0, s>>>(a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const unsigned grid = std::max(kXcds, (std::min(workgroups, 256u * 16u) + kXcds - 1) / kXcds * kXcds);
+    switch (kind) {
+    case MLP_MFMA_F16: return launch_batch_f16(a, sh, grid, s);
+    case MLP_VALU_F32: return launch_batch_f32(a, sh, grid, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_calibrate(const MaterialDesc &m, const MlpShape &sh, const WsLayout &lay, const void *ws,

@@ -295,3 +295,178 @@ def workload_queries(w: Workload, n: int | None = None) -> np.ndarray:
 
 def shuffled(q: np.ndarray) -> np.ndarray:
     return q[rng(SEED_SHUFFLE).permutation(len(q))]
+
+
+# --------------------------------------------------------------------------
+# many materials served together
+
+SEED_BATCH = 5
+
+
+@dataclass(frozen=True)
+class BatchSpec:
+    """Per material: base resolution (4 pyramids sharing it, full chains) and
+    query count; one MLP shape for all, each material its own weights."""
+    res: tuple
+    counts: tuple
+    dims: tuple
+    seed: int
+
+    @property
+    def n_materials(self) -> int:
+        return len(self.res)
+
+    def offsets(self) -> np.ndarray:
+        return np.concatenate([[0], np.cumsum(self.counts)]).astype(np.int64)
+
+
+def batch_spec(n_materials: int = 64, res_choices=(512, 1024, 2048, 4096), log2_counts=(14.0, 22.0),
+               dims=(12, 32, 32, 10), seed: int = SEED_BATCH) -> BatchSpec:
+    """Base resolutions uniform over `res_choices`, query counts log-uniform in
+    [2^lo, 2^hi]."""
+    g = rng(seed)
+    res = tuple(int(r) for r in g.choice(np.asarray(res_choices), size=n_materials))
+    counts = tuple(int(c) for c in np.floor(2.0 ** g.uniform(log2_counts[0], log2_counts[1], n_materials)))
+    return BatchSpec(res, counts, tuple(dims), seed)
+
+
+def block_pool(n: int = 1 << 16, seed: int = SEED_BATCH) -> np.ndarray:
+    """A pool of bounded blocks (variant B) that large batch textures draw from."""
+    return bounded_blocks(n, rng(seed + 1000))
+
+
+def batch_material(spec: BatchSpec, k: int, pool: np.ndarray | None = None) -> Material:
+    """Material k of the batch: every block of its four pyramids is a seeded
+    draw from the bounded-block pool, its MLP seeded by k."""
+    pool = block_pool() if pool is None else pool
+    g = rng(spec.seed * 1000003 + 7 * k + 1)
+    r = spec.res[k]
+    L = full_levels(r, r)
+    n = chain_blocks(r, r, L)
+    texs = [pool[g.integers(0, len(pool), size=n)].reshape(-1) for _ in range(4)]
+    params = mlp_params(spec.dims, rng(spec.seed * 1000003 + 7 * k + 2))
+    return Material(texs, [r] * 4, [L] * 4, spec.dims, params)
+
+
+def batch_queries(spec: BatchSpec, k: int) -> np.ndarray:
+    """Queries of material k: u, v uniform, s uniform over the full chain."""
+    r = spec.res[k]
+    return uniform_queries(spec.counts[k], rng(spec.seed * 1000003 + 7 * k + 3), float(full_levels(r, r) - 1))
+
+
+# --------------------------------------------------------------------------
+# a procedural reference material for training (the target F(M) of eq. 4)
+
+SEED_TARGET = 6
+
+
+def _value_noise(res: int, cells: int, g: np.random.Generator) -> np.ndarray:
+    """Periodic value noise: a cells x cells grid of uniform values, smoothly
+    (cubic Hermite) interpolated up to res x res."""
+    grid = g.random((cells, cells))
+    t = (np.arange(res) + 0.5) * cells / res
+    i0 = np.floor(t).astype(np.int64) % cells
+    i1 = (i0 + 1) % cells
+    f = t - np.floor(t)
+    f = f * f * (3 - 2 * f)
+    rows = grid[i0][:, i0] * (1 - f)[None, :] + grid[i0][:, i1] * f[None, :]
+    rows2 = grid[i1][:, i0] * (1 - f)[None, :] + grid[i1][:, i1] * f[None, :]
+    return rows * (1 - f)[:, None] + rows2 * f[:, None]
+
+
+def fbm(res: int, g: np.random.Generator, octaves: int = 6, base_cells: int = 4) -> np.ndarray:
+    """Fractal sum of value noise, amplitude halving and frequency doubling per octave, in [0, 1]."""
+    out = np.zeros((res, res))
+    amp, total = 1.0, 0.0
+    for o in range(octaves):
+        out += amp * _value_noise(res, min(base_cells << o, res), g)
+        total += amp
+        amp *= 0.5
+    return out / total
+
+
+def procedural_target(res: int = 2048, seed: int = SEED_TARGET) -> list:
+    """A tiling PBR texture set with full mips, float32 [h, w, 10] per level:
+    albedo (3, 6-octave fBm), normal (3, from an fBm height map, in [0, 1]),
+    roughness, metalness, ambient occlusion (thresholded noise) and height."""
+    g = rng(seed)
+    albedo = np.stack([0.05 + 0.9 * fbm(res, g) for _ in range(3)], -1)
+    height = fbm(res, g)
+    dx = (np.roll(height, -1, 1) - np.roll(height, 1, 1)) * res / 16.0
+    dy = (np.roll(height, -1, 0) - np.roll(height, 1, 0)) * res / 16.0
+    nrm = np.stack([-dx, -dy, np.ones_like(height)], -1)
+    nrm = 0.5 + 0.5 * nrm / np.linalg.norm(nrm, axis=-1, keepdims=True)
+
+    def threshold(x, lo, hi):
+        t = np.clip((x - lo) / (hi - lo), 0, 1)
+        return t * t * (3 - 2 * t)
+    rough = threshold(fbm(res, g), 0.35, 0.65)
+    metal = threshold(fbm(res, g), 0.55, 0.6)
+    ao = 1.0 - 0.8 * threshold(1.0 - height, 0.5, 0.9)
+    level = np.concatenate([albedo, nrm, rough[..., None], metal[..., None], ao[..., None], height[..., None]],
+                           -1).astype(np.float32)
+    chain = [level]
+    while chain[-1].shape[0] > 1:
+        a = chain[-1]
+        chain.append(0.25 * (a[0::2, 0::2] + a[1::2, 0::2] + a[0::2, 1::2] + a[1::2, 1::2]))
+    return chain
+
+
+def _catmull_rom(t: np.ndarray) -> np.ndarray:
+    """Catmull-Rom weights [n, 4] for fractional positions t in [0, 1)."""
+    t2, t3 = t * t, t * t * t
+    return np.stack([-0.5 * t3 + t2 - 0.5 * t,
+                     1.5 * t3 - 2.5 * t2 + 1.0,
+                     -1.5 * t3 + 2.0 * t2 + 0.5 * t,
+                     0.5 * t3 - 0.5 * t2], -1)
+
+
+def sample_target(chain: list, queries: np.ndarray) -> np.ndarray:
+    """The reference sampled as the training of Section 5.1 does: bicubic
+    (Catmull-Rom) on the two closest mips, then a linear blend by the
+    fractional scale; wrap addressing. float32 [n, channels]."""
+    q = queries.astype(np.float64)
+    u = q[:, 0] - np.floor(q[:, 0])
+    v = q[:, 1] - np.floor(q[:, 1])
+    s = np.clip(q[:, 2], 0, len(chain) - 1)
+    l0 = np.floor(s).astype(np.int64)
+    l1 = np.minimum(l0 + 1, len(chain) - 1)
+    lam = (s - l0)[:, None]
+    out = np.zeros((len(q), chain[0].shape[-1]))
+
+    def bicubic(level, sel):
+        img = chain[level]
+        h, w = img.shape[:2]
+        x = u[sel] * w - 0.5
+        y = v[sel] * h - 0.5
+        x0, y0 = np.floor(x).astype(np.int64), np.floor(y).astype(np.int64)
+        wx, wy = _catmull_rom(x - x0), _catmull_rom(y - y0)
+        acc = np.zeros((sel.sum(), img.shape[-1]))
+        for j in range(4):
+            yy = (y0 - 1 + j) % h
+            for i in range(4):
+                xx = (x0 - 1 + i) % w
+                acc += (wy[:, j] * wx[:, i])[:, None] * img[yy, xx]
+        return acc
+
+    for level in range(len(chain)):
+        s0 = l0 == level
+        if s0.any():
+            out[s0] += (1 - lam[s0]) * bicubic(level, s0)
+        s1 = l1 == level
+        if s1.any():
+            out[s1] += lam[s1] * bicubic(level, s1)
+    return out.astype(np.float32)
+
+
+def train_problem(res: int = 1024, dims=(12, 32, 32, 10), seed: int = SEED_TARGET + 1):
+    """Continuous two-subset block parameters for four res x res pyramids with
+    full chains (endpoints uniform in [0, 31], so texels stay below 1; indices
+    uniform; partitions uniform) and the MLP parameters."""
+    g = rng(seed)
+    L = full_levels(res, res)
+    nb = chain_blocks(res, res, L)
+    ends = [g.uniform(0.0, 31.0, (nb, 4, 3)).astype(np.float32) for _ in range(4)]
+    idxs = [g.uniform(0.0, 1.0, (nb, 16)).astype(np.float32) for _ in range(4)]
+    parts = [g.integers(0, 32, nb).astype(np.uint8) for _ in range(4)]
+    return ends, idxs, parts, L, mlp_params(dims, g)

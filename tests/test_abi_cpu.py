@@ -207,3 +207,33 @@ def test_train_call_argument_checks(bcf):
     assert bcf.lib.bcf_train_backward(*args, ptrs, nulls, C.c_void_p(FAKE), None) == 1
     assert "texture 2" in bcf.lib.bcf_last_error().decode()
     assert bcf.lib.bcf_train_backward(*args, ptrs, ptrs, None, None) == 1
+
+
+def test_batch_validation(bcf):
+    from paper_2311_16121_amd._lib import _Material
+    mats = [material(bcf), material(bcf, res=(64, 16), levels=5), material(bcf, n_tex=2, dims=(6, 16, 16, 9))]
+    arr = (_Material * 3)(*mats)
+    n = C.c_size_t(0)
+    # dims differ between material 0 and 2
+    assert bcf.lib.bcf_batch_workspace_size(arr, 3, 1, C.byref(n)) == 1
+    assert "material 2" in bcf.lib.bcf_last_error().decode()
+    assert bcf.lib.bcf_batch_workspace_size(arr, 2, 1, C.byref(n)) == 0
+    two = n.value
+    single = C.c_size_t(0)
+    assert bcf.lib.bcf_batch_workspace_size(arr, 1, 1, C.byref(single)) == 0
+    assert two > single.value > 0
+    # precisions other than FP16 / FP32, an empty batch, a bad member
+    assert bcf.lib.bcf_batch_workspace_size(arr, 2, 2, C.byref(n)) == 2
+    assert bcf.lib.bcf_batch_workspace_size(arr, 0, 1, C.byref(n)) == 1
+    bad = (_Material * 2)(mats[0], material(bcf, levels=0))
+    assert bcf.lib.bcf_batch_workspace_size(bad, 2, 0, C.byref(n)) == 1
+    assert "material 1" in bcf.lib.bcf_last_error().decode()
+    # decode argument checks
+    assert bcf.lib.bcf_decode_batch(arr, 2, 1, C.c_void_p(FAKE), C.c_void_p(FAKE), None, 10,
+                                    C.c_void_p(FAKE), None, None) == 1
+    assert bcf.lib.bcf_decode_batch(arr, 2, 1, C.c_void_p(FAKE + 8), C.c_void_p(FAKE), C.c_void_p(FAKE), 10,
+                                    C.c_void_p(FAKE), None, None) == 1
+    assert bcf.lib.bcf_decode_batch(arr, 2, 1, C.c_void_p(FAKE), None, C.c_void_p(FAKE), 10,
+                                    C.c_void_p(FAKE), None, None) == 1
+    assert bcf.lib.bcf_prepare_batch(arr, 2, 1, C.c_void_p(FAKE), 100, None) == 1
+    assert "workspace" in bcf.lib.bcf_last_error().decode()

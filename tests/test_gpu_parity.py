@@ -281,3 +281,22 @@ def test_unpack_then_decode_unpacked_equals_decode(bcf):
     bcf.unpack(mat, ws16)
     got = bcf.decode_unpacked(mat, ws16, qd, bcf.Precision.FP16).cpu().numpy().astype(np.float64)
     assert np.abs(got - oracle.decode(host, q)).max() <= 2e-3
+
+
+@pytest.mark.parametrize("dims", [(12, 32, 32, 10), (12, 16, 9)])
+def test_grid_width_does_not_change_results(bcf, dims):
+    # 8x8 tiles over images with ragged right and bottom edges, widths that are
+    # and are not multiples of 8, rows whose byte length is and is not a
+    # multiple of 16, against the plain run of consecutive queries
+    texs, sizes, lv, params, bias, host = make(64, 7, dims, "B", seed=31)
+    mat = bcf.Material.from_host(texs, sizes, lv, dims, params, bias)
+    g = synth.rng(32)
+    for n, width in ((53 * 37 + 17, 53), (4096, 64), (3000, 8), (999, 999), (5000, 37), (70, 9)):
+        q = synth.uniform_queries(n, g, 6.0)
+        qd = dev(q)
+        for p in ("FP32", "FP16"):
+            prec = bcf.Precision[p]
+            ws = bcf.prepare(mat, prec)
+            flat = bcf.decode(mat, ws, qd, prec).cpu().numpy()
+            tiled = bcf.decode(mat, ws, qd, prec, grid_width=width).cpu().numpy()
+            assert np.array_equal(flat.view(np.uint32), tiled.view(np.uint32)), (n, width, p)

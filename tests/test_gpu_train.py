@@ -9,7 +9,11 @@ Bars:
     float-atomic sums against binary64), excluding in continuous mode the
     blocks with a texel within 0.05 of a step of eq. (8)'s slope.
   * finite differences (continuous mode, binary32 forward, fp64 sums):
-    directional derivatives within 2% of the analytic ones.
+    within 3% of the analytic derivatives, per block-parameter coordinate and
+    along directions in the MLP parameters. The loss is piecewise linear (ReLU,
+    eq. (8)), so a step that crosses a ReLU kink of one of the queries the
+    block feeds moves the difference quotient by up to about a percent; the
+    exact check is the one against the binary64 oracle above.
 """
 import numpy as np
 import pytest
@@ -112,7 +116,11 @@ def test_gradients_match_oracle(bcf, ste, shape):
         close(f"indices[{t}]", g_idx[t], r_idx[t], keep)
 
 
-def test_continuous_directional_derivatives(bcf):
+def test_continuous_finite_differences(bcf):
+    # eq. (8) as printed is exact at integer y but steps by half a unit of the
+    # half's last place at y = 1024 k + 1 between integers, so the differences
+    # are taken per coordinate on blocks whose texels stay clear of those
+    # points, and along a direction in the (smooth) MLP parameters
     texs, dims, params, q, go = problem(421, n=4000)
     geo, ends, idxs, p = to_gpu(bcf, texs, dims, params, False)
     qd, god = dev(q), dev(go)
@@ -123,18 +131,42 @@ def test_continuous_directional_derivatives(bcf):
         out = bcf.train_forward(geo, e, x, pp, qd)
         return float((out.double() * god.double()).sum())
 
+    def clear_blocks(tex, margin):
+        y = T.continuous_y(tex)
+        d = np.abs((y - 1.0) / 1024.0 - np.round((y - 1.0) / 1024.0)) * 1024.0
+        return np.nonzero((d > margin).all(axis=(1, 2)))[0]
+
+    checked = 0
+    for trial in range(12):
+        t = int(g.integers(len(texs)))
+        blocks = clear_blocks(texs[t], 16.0)
+        b = int(blocks[g.integers(len(blocks))])
+        j, c, k = int(g.integers(4)), int(g.integers(3)), int(g.integers(16))
+        # a step moves y by at most a 1024 h (endpoint) or a 31744 h (index): < 16
+        for kind, h in (("endpoint", 1e-2), ("index", 1e-3)):
+            def bumped(sign):
+                e2 = [e.clone() for e in ends]
+                x2 = [x.clone() for x in idxs]
+                if kind == "endpoint":
+                    e2[t][b, j, c] += sign * h
+                else:
+                    x2[t][b, k] += sign * h
+                return loss(e2, x2, p)
+            fd = (bumped(1.0) - bumped(-1.0)) / (2 * h)
+            an = float(g_end[t][b, j, c] if kind == "endpoint" else g_idx[t][b, k])
+            if abs(an) < 1e-3 and abs(fd) < 1e-3:
+                continue                        # the block feeds no query
+            log(f"{kind} t={t} b={b}: fd {fd:.6e} analytic {an:.6e}")
+            assert abs(fd - an) <= 0.03 * abs(an) + 2e-4
+            checked += 1
+    assert checked >= 8
     for trial in range(3):
-        de = [dev(g.standard_normal(e.shape).astype(np.float32)) for e in ends]
-        dx = [dev(0.02 * g.standard_normal(x.shape).astype(np.float32)) for x in idxs]
         dp = dev(0.05 * g.standard_normal(p.shape).astype(np.float32))
-        analytic = sum(float((a.double() * b.double()).sum()) for a, b in zip(g_end + g_idx + [g_par],
-                                                                               de + dx + [dp]))
         h = 1e-2
-        plus = loss([e + h * d for e, d in zip(ends, de)], [x + h * d for x, d in zip(idxs, dx)], p + h * dp)
-        minus = loss([e - h * d for e, d in zip(ends, de)], [x - h * d for x, d in zip(idxs, dx)], p - h * dp)
-        fd = (plus - minus) / (2 * h)
-        log(f"directional derivative {trial}: fd {fd:.6e} analytic {analytic:.6e}")
-        assert abs(fd - analytic) <= 0.02 * abs(analytic)
+        fd = (loss(ends, idxs, p + h * dp) - loss(ends, idxs, p - h * dp)) / (2 * h)
+        an = float((g_par.double() * dp.double()).sum())
+        log(f"MLP direction {trial}: fd {fd:.6e} analytic {an:.6e}")
+        assert abs(fd - an) <= 0.03 * abs(an)
 
 
 def test_ste_forward_equals_product_decode_of_exported_blocks(bcf):
