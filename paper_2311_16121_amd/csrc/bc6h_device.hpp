@@ -282,18 +282,21 @@ __host__ __device__ __forceinline__ void bc6h_header(uint32_t d0, uint32_t d1, u
 template <bool SIGNED>
 __host__ __device__ __forceinline__ uint32_t bc6h_texel(const Bc6hHeader &h, uint32_t t, int c)
 {
-    const uint32_t i = (uint32_t)(h.idx >> (h.ib * t)) & ((1u << h.ib) - 1u);
+    // operands masked to their known widths (no-ops here) so the compiler can
+    // use the full-rate 24-bit multiplies
+    const uint32_t i = (uint32_t)(h.idx >> (h.ib * t)) & ((1u << h.ib) - 1u) & 15u;
     const uint32_t wt = (i * (h.ib == 3 ? 585u : 273u) + 32u) >> 6;
     const uint32_t s = (h.mask >> t) & 1u;
     const int32_t base = s ? h.base[1][c] : h.base[0][c];
-    const int32_t diff = s ? h.diff[1][c] : h.diff[0][c];
-    const int32_t v = (base + (int32_t)wt * diff) >> 6;          // arithmetic: floor
+    // |diff| < 2^17 and wt <= 64
+    const int32_t diff = (int32_t)((uint32_t)(s ? h.diff[1][c] : h.diff[0][c]) << 8) >> 8;
+    const int32_t v = (base + (int32_t)(wt & 127u) * diff) >> 6;   // arithmetic: floor
     uint32_t out;
     if (!SIGNED) {
-        out = ((uint32_t)v * 31u) >> 6;
+        out = (((uint32_t)v & 0xFFFFFFu) * 31u) >> 6;                 // v <= 0xFFFF
     } else {
         const uint32_t m = (uint32_t)(v < 0 ? -v : v);
-        out = ((m * 31u) >> 5) | (v < 0 ? 0x8000u : 0u);
+        out = (((m & 0xFFFFFFu) * 31u) >> 5) | (v < 0 ? 0x8000u : 0u); // |v| <= 0x7FFF
     }
     return h.valid ? out : 0u;
 }

@@ -83,40 +83,47 @@ __device__ __forceinline__ const_float *constant_floats(const uint8_t *p)
     return (const_float *)p;
 }
 
+// Row j of a layer's weights and its bias, through the constant address
+// space (scalar loads, SGPR operands). The pointer goes through an empty asm
+// per row, so the optimiser can neither hoist the loads out of the caller's
+// query loop nor keep more than about a row's weights live: 1-2k weights do
+// not fit in SGPRs and would be spilled.
+__device__ __forceinline__ const_float *weight_row(const uint8_t *ws, size_t off, uint32_t row, uint32_t n_in)
+{
+    asm volatile("" : "+s"(ws));
+    return constant_floats(ws + off) + row * n_in;
+}
+
+template <int N_IN>
+__device__ __forceinline__ float neuron(const uint8_t *ws, const WsLayout &lay, int l, uint32_t j, const float *x)
+{
+    const_float *w = weight_row(ws, lay.layer_w_off[l], j, N_IN);
+    float acc = constant_floats(ws + lay.layer_b_off[l])[j];
+#pragma unroll
+    for (int i = 0; i < N_IN; ++i) acc = fmaf(w[i], x[i], acc);
+    return acc;
+}
+
 template <int H, int NH, int C>
 __device__ __forceinline__ void mlp_valu(const uint8_t *ws, const WsLayout &lay, const float z[12], float o[C],
                                          float *amax)
 {
-    const_float *W = constant_floats(ws + lay.layer_w_off[0]);
-    const_float *B = constant_floats(ws + lay.layer_b_off[0]);
     if (amax) {
 #pragma unroll
         for (int i = 0; i < 12; ++i) amax[0] = fmaxf(amax[0], fabsf(z[i]));
     }
     float hcur[H];
 #pragma unroll
-    for (int j = 0; j < H; ++j) {
-        float acc = B[j];
-#pragma unroll
-        for (int i = 0; i < 12; ++i) acc = fmaf(W[j * 12 + i], z[i], acc);
-        hcur[j] = relu(acc);
-    }
+    for (int j = 0; j < H; ++j) hcur[j] = relu(neuron<12>(ws, lay, 0, j, z));
 #pragma unroll
     for (int l = 1; l < NH; ++l) {
         if (amax) {
 #pragma unroll
             for (int i = 0; i < H; ++i) amax[l] = fmaxf(amax[l], hcur[i]);
         }
-        W = constant_floats(ws + lay.layer_w_off[l]);
-        B = constant_floats(ws + lay.layer_b_off[l]);
         float hn[H];
 #pragma unroll
-        for (int j = 0; j < H; ++j) {
-            float acc = B[j];
-#pragma unroll
-            for (int i = 0; i < H; ++i) acc = fmaf(W[j * H + i], hcur[i], acc);
-            hn[j] = relu(acc);
-        }
+        for (int j = 0; j < H; ++j) hn[j] = relu(neuron<H>(ws, lay, l, j, hcur));
 #pragma unroll
         for (int j = 0; j < H; ++j) hcur[j] = hn[j];
     }
@@ -124,15 +131,8 @@ __device__ __forceinline__ void mlp_valu(const uint8_t *ws, const WsLayout &lay,
 #pragma unroll
         for (int i = 0; i < H; ++i) amax[NH] = fmaxf(amax[NH], hcur[i]);
     }
-    W = constant_floats(ws + lay.layer_w_off[NH]);
-    B = constant_floats(ws + lay.layer_b_off[NH]);
 #pragma unroll
-    for (int j = 0; j < C; ++j) {
-        float acc = B[j];
-#pragma unroll
-        for (int i = 0; i < H; ++i) acc = fmaf(W[j * H + i], hcur[i], acc);
-        o[j] = acc;
-    }
+    for (int j = 0; j < C; ++j) o[j] = neuron<H>(ws, lay, NH, j, hcur);
 }
 
 __device__ __forceinline__ void wave_lds_sync()
@@ -218,7 +218,9 @@ __global__ void __launch_bounds__(kFrameThreads) k_frame(FrameArgs a)
     __shared__ float4_t stage[kFrameWaves][64 * kMaxOut / 4];
     copy_lut(a.lut, lut);
 
-    const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    // the wave index is uniform across the wave: say so, so that everything
+    // derived from it (work items, materials, offsets) lives in SGPRs
+    const uint32_t lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const __amdgpu_buffer_rsrc_t rs = make_rsrc(a.ws + a.lay.scratch_off, (uint32_t)a.lay.scratch_bytes);
     const __amdgpu_buffer_rsrc_t rq = make_rsrc(a.queries, a.n * 12u);
     const __amdgpu_buffer_rsrc_t ro = make_rsrc(a.out, a.n * a.out_dim * 4u);
@@ -307,6 +309,14 @@ __global__ void __launch_bounds__(kFrameThreads) k_calibrate(FrameArgs a)
 // contiguous range of the concatenated query array. Work items are runs of 64
 // queries of one material, numbered material after material.
 
+// A wave-uniform value loaded from memory, moved to SGPRs.
+__device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ uint64_t uniform64(uint64_t v)
+{
+    return ((uint64_t)uniform((uint32_t)(v >> 32)) << 32) | uniform((uint32_t)v);
+}
+
 struct BatchMat {
     LevelLut lut;                          // as FrameArgs, offsets within the material's scratch
     float levels_bias[2 * kMaxTextures];
@@ -342,7 +352,9 @@ __global__ void __launch_bounds__(kFrameThreads) k_batch(BatchArgs a)
     __shared__ LevelLut lut[kFrameWaves];                 // each wave's current material
     __shared__ float4_t feats[VALU ? 1 : kFrameWaves][64][4];
     __shared__ float4_t stage[kFrameWaves][64 * kMaxOut / 4];
-    const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    // the wave index is uniform across the wave: say so, so that everything
+    // derived from it (work items, materials, offsets) lives in SGPRs
+    const uint32_t lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     float *st = reinterpret_cast<float *>(&stage[wv][0]);
     const uint32_t total = a.items[a.n_mats];
 
@@ -373,22 +385,26 @@ __global__ void __launch_bounds__(kFrameThreads) k_batch(BatchArgs a)
             if (a.items[mid] <= it) lo = mid;
             else hi = mid;
         }
+        lo = uniform(lo);
         if (lo != cur) {
             cur = lo;
             const BatchMat &M = a.mats[cur];
             lut[wv].e[lane >> 4][lane & 15] = M.lut.e[lane >> 4][lane & 15];
 #pragma unroll
-            for (int j = 0; j < 2 * kMaxTextures; ++j) lb[j] = M.levels_bias[j];
-            shared = M.shared;
-            stride = M.stride;
-            rs = make_rsrc(a.ws + M.scratch_off, M.scratch_bytes);
+            for (int j = 0; j < 2 * kMaxTextures; ++j)
+                lb[j] = __builtin_bit_cast(float, uniform(__builtin_bit_cast(uint32_t, M.levels_bias[j])));
+            shared = uniform(M.shared);
+            stride = uniform(M.stride);
+            rs = make_rsrc(a.ws + uniform64(M.scratch_off), uniform(M.scratch_bytes));
             uint32_t q0;
             batch_range(a, cur, q0, n_k);
+            q0 = uniform(q0);
+            n_k = uniform(n_k);
             rq = make_rsrc(a.queries + 3ull * q0, n_k * 12u);
             ro = make_rsrc(a.out + (uint64_t)a.out_dim * q0, n_k * a.out_dim * 4u);
-            wbase = a.ws + M.weights_off;
+            wbase = a.ws + uniform64(M.weights_off);
             if (!VALU) mlp.load(wbase, a.lay, lane);
-            first_item = a.items[cur];
+            first_item = uniform(a.items[cur]);
             wave_lds_sync();
         }
         const uint32_t j = it - first_item;
