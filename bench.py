@@ -342,6 +342,59 @@ def bench_train(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_sweep(args):
+    """Every MLP precision on the precision-sweep workload: 4 x 256^2 pyramids
+    (bounded blocks), MLP 12-64-64-10, 2^24 uniform queries. One line, the
+    FP8 rate as the value; each precision's rate and its MLP's share of the
+    MFMA peak alongside (errors: tests/test_gpu_precision_sweep.py)."""
+    import torch
+
+    import paper_2311_16121_amd as bcf
+    import synth
+
+    wl = synth.WORKLOADS["sweep"]
+    m = synth.workload_material(wl, variant="B")
+    q = synth.workload_queries(wl)
+    mat = bcf.Material.from_host(m.textures, m.res, m.levels, m.dims, m.params)
+    qd = torch.from_numpy(q).cuda()
+    calib = synth.uniform_queries(1 << 16, synth.rng(1234), wl.s_max)
+    mat.set_act_absmax(bcf.calibrate(mat, torch.from_numpy(calib).cuda()))
+    n = len(q)
+    out = torch.empty((n, m.dims[-1]), dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+    flops = 2 * sum(a * b for a, b in zip(m.dims[:-1], m.dims[1:])) * n      # MLP multiply-adds x 2
+    peaks = {"FP32": 78.6, "FP32_MFMA": 157.3, "FP16": 2500.0, "BF16": 2500.0, "FP8": 5000.0}   # TFLOP/s
+    rates = {}
+    for name in ("FP32", "FP32_MFMA", "FP16", "BF16", "FP8"):
+        prec = bcf.Precision[name]
+        ws = bcf.prepare(mat, prec)
+        bcf.unpack(mat, ws)
+        for _ in range(args.warmup):
+            bcf.decode_unpacked(mat, ws, qd, prec, out=out)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(args.steps):
+            bcf.decode_unpacked(mat, ws, qd, prec, out=out)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        rates[name] = {"queries_per_s": n / (ms * 1e-3), "ms": ms,
+                       "mlp_tflops": flops / (ms * 1e-3) / 1e12,
+                       "mlp_frac_of_peak": flops / (ms * 1e-3) / 1e12 / peaks[name]}
+        del ws
+    line = {
+        "metric": "decoded queries/s per MLP precision (filter + MLP from unpacked texels)",
+        "value": rates["FP8"]["queries_per_s"], "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": rates["FP8"]["ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "fp8", "data": "synthetic",
+        "config": {"workload": "sweep: 4 x 256^2 BC6H pyramids (9 levels, bounded), MLP 12-64-64-10, "
+                               "2^24 uniform queries", "queries": n},
+        "precisions": rates,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -351,7 +404,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first run a plain copy of this many MiB (to scale memory counters)")
-    ap.add_argument("--workload", default="frame4k", choices=("frame4k", "batch64", "train"),
+    ap.add_argument("--workload", default="frame4k", choices=("frame4k", "batch64", "train", "sweep"),
                     help="frame4k: the full-frame decode (default); batch64: 64 materials in one launch; "
                          "train: a straight-through training step")
     args = ap.parse_args()
@@ -370,6 +423,8 @@ def main():
         return bench_batch(args)
     if args.workload == "train":
         return bench_train(args)
+    if args.workload == "sweep":
+        return bench_sweep(args)
     wl = synth.WORKLOADS["frame4k"]
     log("generating workload")
     m = synth.workload_material(wl, variant="B")

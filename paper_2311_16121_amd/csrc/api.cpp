@@ -272,6 +272,13 @@ bcf_status describe_train(const bcf_train_material *m, bcf::TrainDesc *d, size_t
             td.tex_off[l] = (uint32_t)texels;
             texels += (size_t)level_dim(x.width, l) * level_dim(x.height, l);
         }
+        // the smallest levels that together hold at most kTrainSmallTexels texels
+        d->small_hi[t] = (uint32_t)texels;
+        d->small_lo[t] = (uint32_t)texels;
+        for (uint32_t l = x.levels; l-- > 0;) {
+            if (texels - td.tex_off[l] > bcf::kTrainSmallTexels) break;
+            d->small_lo[t] = td.tex_off[l];
+        }
     }
     d->blk_base[m->n_textures] = (uint32_t)blocks;
     if (texels > ((size_t)1 << 27)) return fail(BCF_ERR_UNSUPPORTED, "%zu texels, at most 2^27", texels);
@@ -306,10 +313,11 @@ bcf_status describe_train(const bcf_train_material *m, bcf::TrainDesc *d, size_t
     return BCF_OK;
 }
 
-bcf_status bind_train_ws(bcf::TrainDesc *d, void *ws, size_t ws_bytes)
+// The workspace holds bcf_train_workspace_size bytes (the caller's promise):
+// the texel values, then their gradients.
+bcf_status bind_train_ws(bcf::TrainDesc *d, void *ws)
 {
     if (!ws || !aligned(ws, 256)) return fail(BCF_ERR_INVALID_ARG, "workspace NULL or not 256-byte aligned");
-    (void)ws_bytes;
     uint8_t *p = static_cast<uint8_t *>(ws);
     d->texels = reinterpret_cast<float4 *>(p);
     d->g_texels = reinterpret_cast<float4 *>(p + align_up((size_t)d->n_texels * 16, 256));
@@ -499,7 +507,7 @@ bcf_status bcf_train_forward(const bcf_train_material *m, void *ws, const float 
     bcf_status st = describe_train(m, &d, &need);
     if (st != BCF_OK) return st;
     if (n == 0) return BCF_OK;
-    if ((st = bind_train_ws(&d, ws, need)) != BCF_OK) return st;
+    if ((st = bind_train_ws(&d, ws)) != BCF_OK) return st;
     if (!queries || !aligned(queries, 4)) return fail(BCF_ERR_INVALID_ARG, "queries NULL or misaligned");
     if (!out || !aligned(out, 4)) return fail(BCF_ERR_INVALID_ARG, "out NULL or misaligned");
     if (n > bcf::kMaxQueriesPerLaunch) return fail(BCF_ERR_UNSUPPORTED, "n = %zu, at most 2^25", n);
@@ -515,7 +523,7 @@ bcf_status bcf_train_backward(const bcf_train_material *m, void *ws, const float
     size_t need;
     bcf_status st = describe_train(m, &d, &need);
     if (st != BCF_OK) return st;
-    if ((st = bind_train_ws(&d, ws, need)) != BCF_OK) return st;
+    if ((st = bind_train_ws(&d, ws)) != BCF_OK) return st;
     if (n > 0 && (!queries || !aligned(queries, 4) || !grad_out || !aligned(grad_out, 4)))
         return fail(BCF_ERR_INVALID_ARG, "queries or grad_out NULL or misaligned");
     if (n > bcf::kMaxQueriesPerLaunch) return fail(BCF_ERR_UNSUPPORTED, "n = %zu, at most 2^25", n);

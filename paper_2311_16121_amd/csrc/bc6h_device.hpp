@@ -301,4 +301,51 @@ __host__ __device__ __forceinline__ uint32_t bc6h_texel(const Bc6hHeader &h, uin
     return h.valid ? out : 0u;
 }
 
+// The at most 16 distinct values a block's texels take, channels packed as
+// (r | g << 16, b): entry j = 8 s + i for two-subset modes (3-bit index i of
+// subset s), j = i for one-subset modes (4-bit index i). Each entry is the
+// blend and finish of bc6h_texel for that subset and index.
+template <bool SIGNED>
+__host__ __device__ __forceinline__ void bc6h_palette(const Bc6hHeader &h, uint32_t pal[16][2])
+{
+    const bool two = h.ib == 3;
+    // entries 0..7 blend subset 0; entries 8..15 subset 1 (two subsets) or
+    // subset 0 again (one subset). A reserved mode decodes to zeros: base and
+    // diff 0 give v = 0. |diff| < 2^17 and wt <= 64, so the products fit the
+    // 24-bit multiply once diff is restated as a 24-bit value.
+    int32_t b_lo[3], d_lo[3], b_hi[3], d_hi[3];
+    for (int c = 0; c < 3; ++c) {
+        const int32_t db0 = (int32_t)((uint32_t)h.diff[0][c] << 8) >> 8;
+        const int32_t db1 = (int32_t)((uint32_t)h.diff[1][c] << 8) >> 8;
+        b_lo[c] = h.valid ? h.base[0][c] : 0;
+        d_lo[c] = h.valid ? db0 : 0;
+        b_hi[c] = h.valid ? (two ? h.base[1][c] : h.base[0][c]) : 0;
+        d_hi[c] = h.valid ? (two ? db1 : db0) : 0;
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < 16; ++j) {
+        const int32_t wt = (int32_t)(two ? (((j & 7u) * 585u + 32u) >> 6) : ((j * 273u + 32u) >> 6));
+        uint32_t ch[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int32_t v = ((j < 8 ? b_lo[c] : b_hi[c]) + wt * (j < 8 ? d_lo[c] : d_hi[c])) >> 6;
+            if (!SIGNED) {
+                ch[c] = (((uint32_t)v & 0xFFFFFFu) * 31u) >> 6;                      // v <= 0xFFFF
+            } else {
+                const uint32_t m = (uint32_t)(v < 0 ? -v : v);
+                ch[c] = (((m & 0xFFFFFFu) * 31u) >> 5) | (v < 0 ? 0x8000u : 0u);    // |v| <= 0x7FFF
+            }
+        }
+        pal[j][0] = ch[0] | (ch[1] << 16);
+        pal[j][1] = ch[2];
+    }
+}
+
+// Palette entry of texel t (0..15).
+__host__ __device__ __forceinline__ uint32_t bc6h_slot(const Bc6hHeader &h, uint32_t t)
+{
+    const uint32_t i = (uint32_t)(h.idx >> (h.ib * t)) & ((1u << h.ib) - 1u);
+    return h.ib == 3 ? ((((h.mask >> t) & 1u) << 3) | i) : i;
+}
+
 }  // namespace bcf

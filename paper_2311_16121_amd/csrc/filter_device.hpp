@@ -87,13 +87,11 @@ __device__ __forceinline__ Footprint footprint(uint4 e, float uf, float vf, floa
     return f;
 }
 
-// acc[0..2] += the footprint's weighted texels, the level starting `shift`
-// bytes after the footprint's own base
-__device__ __forceinline__ void gather(__amdgpu_buffer_rsrc_t rs, const Footprint &f, uint32_t shift,
-                                      float *acc)
+typedef uint32_t texel_pair __attribute__((ext_vector_type(4)));   // two 8-byte texels
+
+// acc[0..2] += the footprint's weighted texels from its two fetched rows
+__device__ __forceinline__ void blend(const Footprint &f, texel_pair r0, texel_pair r1, float *acc)
 {
-    const auto r0 = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(f.o0 + shift), 0, 0);
-    const auto r1 = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(f.o1 + shift), 0, 0);
     acc[0] = fmaf(f.w00, half_lo(r0[0]), acc[0]);
     acc[0] = fmaf(f.w10, half_lo(r0[2]), acc[0]);
     acc[0] = fmaf(f.w01, half_lo(r1[0]), acc[0]);
@@ -106,6 +104,16 @@ __device__ __forceinline__ void gather(__amdgpu_buffer_rsrc_t rs, const Footprin
     acc[2] = fmaf(f.w10, half_lo(r0[3]), acc[2]);
     acc[2] = fmaf(f.w01, half_lo(r1[1]), acc[2]);
     acc[2] = fmaf(f.w11, half_lo(r1[3]), acc[2]);
+}
+
+// acc[0..2] += the footprint's weighted texels, the level starting `shift`
+// bytes after the footprint's own base
+__device__ __forceinline__ void gather(__amdgpu_buffer_rsrc_t rs, const Footprint &f, uint32_t shift,
+                                      float *acc)
+{
+    const texel_pair r0 = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(f.o0 + shift), 0, 0);
+    const texel_pair r1 = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(f.o1 + shift), 0, 0);
+    blend(f, r0, r1, acc);
 }
 
 // z[3t + c] = T_t(u, v, s) channel c for the four pyramid slots (slots past

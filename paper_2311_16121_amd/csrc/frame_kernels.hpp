@@ -25,6 +25,11 @@ typedef uint32_t uint4_t __attribute__((ext_vector_type(4)));
 
 constexpr int kFrameThreads = 256;
 constexpr int kFrameWaves = kFrameThreads / 64;
+// 16-byte output chunks per lane of a 64-query item (64 rows of <= 16 floats)
+constexpr int kTileChunks = 64 * kMaxOut / 4 / 64;
+
+// a wave's 64 feature vectors (4 x float4 each) fit its output stage
+static_assert(64 * 4 <= 64 * kMaxOut / 4, "feature vectors must fit the output stage");
 
 struct FrameArgs {
     LevelLut lut;
@@ -38,15 +43,16 @@ struct FrameArgs {
     uint32_t out_dim;
     float *absmax;                         // k_calibrate: per-layer largest |input|
     // 2D work items: with grid_w > 0 the queries are image rows of grid_w and
-    // a wave takes an 8x8 tile (lane = 8 row + column); with 0, 64 consecutive
-    // queries. rows_b128: grid_w * out_dim is a multiple of 4 (16-byte rows)
-    uint32_t grid_w, tiles_x, n_items, rows_b128;
+    // a wave takes a tile of 2^tile_log2 columns by 64 / 2^tile_log2 rows
+    // (lane = row * width + column); with 0, 64 consecutive queries.
+    // rows_b128: grid_w * out_dim is a multiple of 4 (16-byte rows)
+    uint32_t grid_w, tiles_x, n_items, rows_b128, tile_log2;
 };
 
-// Workgroups are dispatched to the 8 XCDs round-robin (workgroup b runs on XCD
-// b % 8), each XCD with its own L2. The workgroups of one XCD take a
-// contiguous band of the work items, so neighbouring items -- which read
-// overlapping texels -- share that L2. The grid is a multiple of 8.
+// The grid is a multiple of the 8 XCDs (workgroups are dispatched to them
+// round-robin). Work items go round-robin over all waves, so the waves on the
+// chip at any moment work on neighbouring items (measured faster than giving
+// each XCD its own band: the bands differ in how often they miss L2).
 constexpr uint32_t kXcds = 8;
 
 struct ItemRange {
@@ -55,10 +61,7 @@ struct ItemRange {
 
 __device__ __forceinline__ ItemRange wave_items(uint32_t n_items, uint32_t wv)
 {
-    const uint32_t xcd = blockIdx.x % kXcds, local = blockIdx.x / kXcds;
-    const uint32_t lo = (uint32_t)((uint64_t)n_items * xcd / kXcds);
-    const uint32_t hi = (uint32_t)((uint64_t)n_items * (xcd + 1) / kXcds);
-    return ItemRange{lo + local * kFrameWaves + wv, hi, (gridDim.x / kXcds) * kFrameWaves};
+    return ItemRange{blockIdx.x * kFrameWaves + wv, n_items, gridDim.x * kFrameWaves};
 }
 
 struct Query {
@@ -150,19 +153,17 @@ __device__ __forceinline__ void copy_lut(const LevelLut &src, LevelLut &dst)
     __syncthreads();
 }
 
-// One wave's 64 queries: filter (eqs. 9, 10), concatenate, MLP (eq. 3); the
-// outputs land in the wave's LDS stage, lane L's at st[L * out_dim ...].
-template <MlpKind K, int H, int NH, int C, bool SHARED>
-__device__ __forceinline__ void decode_wave(const Query &qq, __amdgpu_buffer_rsrc_t rs, const LevelLut &lut,
-                                            const float *levels_bias, uint32_t stride, const uint8_t *wbase,
-                                            const WsLayout &lay,
-                                            const MfmaMlp<K == MLP_VALU_F32 ? MLP_MFMA_F16 : K, H, NH> &mlp,
-                                            float4_t (*feats)[4], float *st, uint32_t out_dim, uint32_t lane)
+// MLP (eq. 3) of a wave's 64 feature vectors z (one per lane); the outputs
+// land in the wave's LDS stage, lane L's at st[L * out_dim ...]. The MFMA path
+// passes the feature vectors through `feats`, which may be the same LDS as st
+// (both 4 KB).
+template <MlpKind K, int H, int NH, int C>
+__device__ __forceinline__ void mlp_stage(const float z[12], const uint8_t *wbase, const WsLayout &lay,
+                                          const MfmaMlp<K == MLP_VALU_F32 ? MLP_MFMA_F16 : K, H, NH> &mlp,
+                                          float4_t (*feats)[4], float *st, uint32_t out_dim, uint32_t lane)
 {
     constexpr bool VALU = K == MLP_VALU_F32;
     const uint32_t g = lane >> 4, qi = lane & 15;
-    float z[12];
-    filter4<SHARED>(rs, lut, levels_bias, stride, qq.u, qq.v, qq.s, z);
     if (VALU) {
         float o[C];
         mlp_valu<H, NH, C>(wbase, lay, z, o, nullptr);
@@ -176,10 +177,13 @@ __device__ __forceinline__ void decode_wave(const Query &qq, __amdgpu_buffer_rsr
             feats[lane][t] = v4;
         }
         wave_lds_sync();
+        float4_t fin[4];
+#pragma unroll
+        for (int grp = 0; grp < 4; ++grp) fin[grp] = feats[16 * grp + qi][g];
+        wave_lds_sync();                      // feats and st share the wave's LDS
 #pragma unroll
         for (int grp = 0; grp < 4; ++grp) {
-            const float4_t f4 = feats[16 * grp + qi][g];
-            const float f[4] = {f4[0], f4[1], f4[2], f4[3]};
+            const float f[4] = {fin[grp][0], fin[grp][1], fin[grp][2], fin[grp][3]};
             const float4_t o4 = mlp.run(f);
             const uint32_t row = (16 * grp + qi) * out_dim;
 #pragma unroll
@@ -188,6 +192,19 @@ __device__ __forceinline__ void decode_wave(const Query &qq, __amdgpu_buffer_rsr
         }
     }
     wave_lds_sync();
+}
+
+// One wave's 64 queries: filter (eqs. 9, 10), concatenate, MLP.
+template <MlpKind K, int H, int NH, int C, bool SHARED>
+__device__ __forceinline__ void decode_wave(const Query &qq, __amdgpu_buffer_rsrc_t rs, const LevelLut &lut,
+                                            const float *levels_bias, uint32_t stride, const uint8_t *wbase,
+                                            const WsLayout &lay,
+                                            const MfmaMlp<K == MLP_VALU_F32 ? MLP_MFMA_F16 : K, H, NH> &mlp,
+                                            float4_t (*feats)[4], float *st, uint32_t out_dim, uint32_t lane)
+{
+    float z[12];
+    filter4<SHARED>(rs, lut, levels_bias, stride, qq.u, qq.v, qq.s, z);
+    mlp_stage<K, H, NH, C>(z, wbase, lay, mlp, feats, st, out_dim, lane);
 }
 
 // Item `it` of a run of n consecutive queries: its (up to) 64 staged rows go
@@ -214,7 +231,7 @@ __global__ void __launch_bounds__(kFrameThreads) k_frame(FrameArgs a)
 {
     constexpr bool VALU = K == MLP_VALU_F32;
     __shared__ LevelLut lut;
-    __shared__ float4_t feats[VALU ? 1 : kFrameWaves][64][4];
+    // per wave 4 KB: the feature vectors, then the staged output rows
     __shared__ float4_t stage[kFrameWaves][64 * kMaxOut / 4];
     copy_lut(a.lut, lut);
 
@@ -227,44 +244,66 @@ __global__ void __launch_bounds__(kFrameThreads) k_frame(FrameArgs a)
     MfmaMlp<VALU ? MLP_MFMA_F16 : K, H, NH> mlp;
     if (!VALU) mlp.load(a.ws, a.lay, lane);
     float *st = reinterpret_cast<float *>(&stage[wv][0]);
+    float4_t (*feats)[4] = reinterpret_cast<float4_t (*)[4]>(&stage[wv][0]);
 
-    const ItemRange items = wave_items(a.n_items, wv);
-    for (uint32_t it = items.first; it < items.end; it += items.step) {
-        // this lane's query; lanes outside the image or past n read zeros
-        // (buffer range check) and their rows are not stored
-        uint32_t q, row0 = 0, col0 = 0;
-        if (a.grid_w) {
-            row0 = (it / a.tiles_x) * 8u;
-            col0 = (it % a.tiles_x) * 8u;
-            const uint32_t col = col0 + (lane & 7u);
-            q = (row0 + (lane >> 3)) * a.grid_w + col;
-            q = col < a.grid_w && q < a.n ? q : a.n;
-        } else {
-            q = it * 64 + lane;
+    // Full tiles store each row of tile_w * out_dim floats as 16-byte chunks;
+    // chunk k = lane + 64 m sits at tile_off[m] bytes from the tile's first
+    // output (all-ones: no such chunk).
+    const uint32_t tile_w = 1u << a.tile_log2, tile_h = 64u >> a.tile_log2;
+    uint32_t tile_off[kTileChunks];
+    {
+        const uint32_t per_row = (tile_w * a.out_dim) >> 2;
+#pragma unroll
+        for (int m = 0; m < kTileChunks; ++m) {
+            const uint32_t k = lane + 64u * m, r = k / per_row, c = k - r * per_row;
+            tile_off[m] = k < 16u * a.out_dim ? r * a.grid_w * a.out_dim * 4u + 16u * c : 0xFFFFFFFFu;
         }
-        const Query qq = load_query(rq, q);
-        decode_wave<K, H, NH, C, SHARED>(qq, rs, lut, a.levels_bias, a.stride, a.ws, a.lay, mlp, feats[VALU ? 0 : wv],
-                                         st, a.out_dim, lane);
-        // Staged rows: lane L's outputs at st[L * out_dim ...]. A run of 8 (tile
-        // row) or 64 (consecutive queries) lanes is one contiguous span of out.
-        const uint32_t chunks = 16 * a.out_dim;          // 64 rows of out_dim floats in 16 bytes
+    }
+    // this lane's query of item `it` (and the item's tile origin); lanes
+    // outside the image or past n read zeros (buffer range check) and their
+    // rows are not stored
+    auto query_of = [&](uint32_t it, uint32_t &row0, uint32_t &col0) -> uint32_t {
+        if (!a.grid_w) {
+            row0 = col0 = 0;
+            return it * 64 + lane;
+        }
+        row0 = (it / a.tiles_x) * tile_h;
+        col0 = (it % a.tiles_x) * tile_w;
+        const uint32_t col = col0 + (lane & (tile_w - 1u));
+        const uint32_t q = (row0 + (lane >> a.tile_log2)) * a.grid_w + col;
+        return col < a.grid_w && q < a.n ? q : a.n;
+    };
+    const ItemRange items = wave_items(a.n_items, wv);
+    uint32_t row0, col0;
+    // the next item's query is loaded while this item's texels are fetched
+    Query next = load_query(rq, query_of(items.first < items.end ? items.first : 0, row0, col0));
+    for (uint32_t it = items.first; it < items.end; it += items.step) {
+        query_of(it, row0, col0);
+        const Query qq = next;
+        if (it + items.step < items.end) {
+            uint32_t r, c;
+            next = load_query(rq, query_of(it + items.step, r, c));
+        }
+        decode_wave<K, H, NH, C, SHARED>(qq, rs, lut, a.levels_bias, a.stride, a.ws, a.lay, mlp, feats, st,
+                                         a.out_dim, lane);
+        // Staged rows: lane L's outputs at st[L * out_dim ...]. A tile row or a
+        // run of 64 consecutive queries is one contiguous span of out.
         if (!a.grid_w) {
             store_run(stage[wv], ro, it, a.n, a.out_dim, lane);
         } else {
-            const bool full = col0 + 8u <= a.grid_w && (row0 + 7u) * a.grid_w + col0 + 8u <= a.n;
+            const bool full = col0 + tile_w <= a.grid_w && (row0 + tile_h - 1u) * a.grid_w + col0 + tile_w <= a.n;
             if (full && a.rows_b128) {
-                const uint32_t per_row = 2u * a.out_dim;     // 8 rows of out_dim floats in 16 bytes
-                for (uint32_t k = lane; k < chunks; k += 64) {
-                    const uint32_t r = k / per_row, c = k - r * per_row;
-                    const uint32_t off = ((row0 + r) * a.grid_w + col0) * a.out_dim * 4u + 16u * c;
-                    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(uint4_t, stage[wv][k]), ro, (int)off,
-                                                           0, 0);
-                }
+                const uint32_t base = (row0 * a.grid_w + col0) * a.out_dim * 4u;
+#pragma unroll
+                for (int m = 0; m < kTileChunks; ++m)
+                    if (tile_off[m] != 0xFFFFFFFFu)
+                        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(uint4_t, stage[wv][lane + 64 * m]),
+                                                               ro, (int)(base + tile_off[m]), 0, 0);
             } else {                                   // an edge tile
                 for (uint32_t k = lane; k < 64u * a.out_dim; k += 64) {
                     const uint32_t src = k / a.out_dim, j = k - src * a.out_dim;
-                    const uint32_t col = col0 + (src & 7u);
-                    const uint32_t qq2 = (row0 + (src >> 3)) * a.grid_w + col;
+                    const uint32_t col = col0 + (src & (tile_w - 1u));
+                    const uint32_t qq2 = (row0 + (src >> a.tile_log2)) * a.grid_w + col;
                     if (col < a.grid_w && qq2 < a.n)
                         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, st[k]), ro,
                                                               (int)((qq2 * a.out_dim + j) * 4u), 0, 0);
@@ -350,12 +389,12 @@ __global__ void __launch_bounds__(kFrameThreads) k_batch(BatchArgs a)
 {
     constexpr bool VALU = K == MLP_VALU_F32;
     __shared__ LevelLut lut[kFrameWaves];                 // each wave's current material
-    __shared__ float4_t feats[VALU ? 1 : kFrameWaves][64][4];
-    __shared__ float4_t stage[kFrameWaves][64 * kMaxOut / 4];
+    __shared__ float4_t stage[kFrameWaves][64 * kMaxOut / 4];   // features, then output rows
     // the wave index is uniform across the wave: say so, so that everything
     // derived from it (work items, materials, offsets) lives in SGPRs
     const uint32_t lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     float *st = reinterpret_cast<float *>(&stage[wv][0]);
+    float4_t (*feats)[4] = reinterpret_cast<float4_t (*)[4]>(&stage[wv][0]);
     const uint32_t total = a.items[a.n_mats];
 
     ItemRange items;
@@ -410,10 +449,10 @@ __global__ void __launch_bounds__(kFrameThreads) k_batch(BatchArgs a)
         const uint32_t j = it - first_item;
         const Query qq = load_query(rq, j * 64 + lane);   // past n_k: zeros, not stored
         if (shared)
-            decode_wave<K, H, NH, C, true>(qq, rs, lut[wv], lb, stride, wbase, a.lay, mlp, feats[VALU ? 0 : wv], st,
+            decode_wave<K, H, NH, C, true>(qq, rs, lut[wv], lb, stride, wbase, a.lay, mlp, feats, st,
                                            a.out_dim, lane);
         else
-            decode_wave<K, H, NH, C, false>(qq, rs, lut[wv], lb, stride, wbase, a.lay, mlp, feats[VALU ? 0 : wv], st,
+            decode_wave<K, H, NH, C, false>(qq, rs, lut[wv], lb, stride, wbase, a.lay, mlp, feats, st,
                                             a.out_dim, lane);
         store_run(stage[wv], ro, j, n_k, a.out_dim, lane);
         wave_lds_sync();

@@ -81,6 +81,9 @@ template <bool SIGNED>
 __global__ void __launch_bounds__(256) k_predecode(PredecodeArgs a)
 {
     __shared__ uint32_t table[kTableWords];
+    // each lane's block palette, entry-major so that lane L's entries sit in
+    // consecutive 8-byte slots across lanes
+    __shared__ uint2 palette[16][256];
     load_table(table);
     // segment of this workgroup (uniform scan over at most 64 entries)
     const uint32_t wg = blockIdx.x;
@@ -95,6 +98,12 @@ __global__ void __launch_bounds__(256) k_predecode(PredecodeArgs a)
     const uint4 b = T.blocks[T.blk_off[l] + bi];
     Bc6hHeader h;
     bc6h_header<SIGNED>(b.x, b.y, b.z, b.w, table, h);
+    {
+        uint32_t pal[16][2];
+        bc6h_palette<SIGNED>(h, pal);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) palette[j][threadIdx.x] = make_uint2(pal[j][0], pal[j][1]);
+    }
     const uint32_t x0 = 4 * (bi % bx), y0 = 4 * (bi / bx);
     const uint32_t pitch = row_pitch(lw);
     uint2 *dst = a.texels + T.tex_off[l];
@@ -105,11 +114,7 @@ __global__ void __launch_bounds__(256) k_predecode(PredecodeArgs a)
         if (y0 + r >= lh) break;
         uint2 px[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const uint32_t t = 4 * r + c;
-            px[c].x = bc6h_texel<SIGNED>(h, t, 0) | bc6h_texel<SIGNED>(h, t, 1) << 16;
-            px[c].y = bc6h_texel<SIGNED>(h, t, 2);
-        }
+        for (int c = 0; c < 4; ++c) px[c] = palette[bc6h_slot(h, 4 * r + c)][threadIdx.x];
         uint2 *row = dst + (size_t)(y0 + r) * pitch;
         if (lw >= 4) {
             // the level starts on a multiple of 4 texels and pitch = w + 2 is
@@ -346,6 +351,9 @@ static FrameArgs frame_args(const MaterialDesc &m, const WsLayout &lay, const vo
     return a;
 }
 
+// Tile width (log2) for queries declared as an image: 16 x 4 tiles.
+constexpr uint32_t kTileLog2 = 4;
+
 // Persistent waves: at most 16 workgroups of 4 waves per CU, a multiple of the XCD count.
 static unsigned frame_grid(uint32_t items)
 {
@@ -369,16 +377,18 @@ hipError_t launch_filter_mlp(const MaterialDesc &m, const MlpShape &sh, MlpKind 
         default: return hipErrorInvalidValue;
         }
     };
-    if (grid_width >= 8 && grid_width <= n && n <= kMaxQueriesPerLaunch) {
-        // an image of grid_width columns: 8x8 tiles, so a wave's queries read
-        // overlapping texels in both directions
+    const uint32_t tile_w = 1u << kTileLog2, tile_h = 64u >> kTileLog2;
+    if (grid_width >= tile_w && grid_width <= n && n <= kMaxQueriesPerLaunch) {
+        // an image of grid_width columns: tiles of several rows, so a wave's
+        // queries read overlapping texels in both directions
         const uint32_t rows = (uint32_t)((n + grid_width - 1) / grid_width);
         a.queries = queries;
         a.out = out;
         a.n = (uint32_t)n;
         a.grid_w = grid_width;
-        a.tiles_x = (grid_width + 7) / 8;
-        a.n_items = a.tiles_x * ((rows + 7) / 8);
+        a.tile_log2 = kTileLog2;
+        a.tiles_x = (grid_width + tile_w - 1) / tile_w;
+        a.n_items = a.tiles_x * ((rows + tile_h - 1) / tile_h);
         a.rows_b128 = (grid_width * sh.out) % 4 == 0;
         return launch(frame_grid(a.n_items));
     }

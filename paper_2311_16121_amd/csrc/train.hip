@@ -25,7 +25,10 @@ namespace {
 
 constexpr float kA = 31.0f / 64.0f;      // a of eq. (6) for the unsigned format
 constexpr int kTrainThreads = 256;
-constexpr int kTrainWaves = kTrainThreads / 64;
+// the backward runs two waves per workgroup: its LDS (per-wave reduction
+// buffers plus the privatised small levels) then fits three workgroups per CU
+constexpr int kBwdThreads = 128;
+constexpr int kBwdWaves = kBwdThreads / 64;
 
 __global__ void __launch_bounds__(256) k_train_zero(float *p, uint32_t n)
 {
@@ -345,14 +348,20 @@ __device__ __forceinline__ void flush(const float acc[K], float *g, uint32_t n_i
 }
 
 template <int H, int NH>
-__global__ void __launch_bounds__(kTrainThreads) k_train_backward(TrainDesc d, const float *queries, uint32_t n,
-                                                                  const float *grad_out)
+__global__ void __launch_bounds__(kBwdThreads, 2) k_train_backward(TrainDesc d, const float *queries, uint32_t n,
+                                                                const float *grad_out)
 {
     constexpr int K0 = entries_per_lane(12, H);
     constexpr int KH = entries_per_lane(H, H);
     constexpr int KL = entries_per_lane(H, kMaxOut);
-    __shared__ float lds_a[kTrainWaves][64][kTrainMaxHidden + 1];
-    __shared__ float lds_d[kTrainWaves][64][kTrainMaxHidden];
+    __shared__ float lds_a[kBwdWaves][64][kTrainMaxHidden + 1];
+    __shared__ float lds_d[kBwdWaves][64][kTrainMaxHidden];
+    // Gradients of each pyramid's smallest levels (texels small_lo..small_hi):
+    // every query that reaches them hits the same few texels, so they are
+    // summed in LDS per workgroup and added to memory once at the end.
+    __shared__ float small[kMaxTextures * kTrainSmallTexels * 3];
+    for (uint32_t i = threadIdx.x; i < kMaxTextures * kTrainSmallTexels * 3; i += kBwdThreads) small[i] = 0.0f;
+    __syncthreads();
 
     const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
     const uint32_t n0 = d.dims[0], c = d.dims[NH + 1];
@@ -370,7 +379,7 @@ __global__ void __launch_bounds__(kTrainThreads) k_train_backward(TrainDesc d, c
     float (*a)[kTrainMaxHidden + 1] = lds_a[wv];
     float (*dl)[kTrainMaxHidden] = lds_d[wv];
     const uint32_t n_chunks = (n + 63u) / 64u;
-    for (uint32_t ch = blockIdx.x * kTrainWaves + wv; ch < n_chunks; ch += gridDim.x * kTrainWaves) {
+    for (uint32_t ch = blockIdx.x * kBwdWaves + wv; ch < n_chunks; ch += gridDim.x * kBwdWaves) {
         const uint32_t q = ch * 64u + lane;
         const bool live = q < n;
         const float u = live ? queries[3u * q] : 0.0f;
@@ -444,13 +453,27 @@ __global__ void __launch_bounds__(kTrainThreads) k_train_backward(TrainDesc d, c
             for (int k = 0; k < 32; ++k) {
                 const int t = k / 8;
                 if (t < (int)d.n_tex) {
-                    float *gp = reinterpret_cast<float *>(d.g_texels + idx[k]);
-                    unsafeAtomicAdd(gp + 0, wt[k] * dz[3 * t + 0]);
-                    unsafeAtomicAdd(gp + 1, wt[k] * dz[3 * t + 1]);
-                    unsafeAtomicAdd(gp + 2, wt[k] * dz[3 * t + 2]);
+                    const uint32_t rel = idx[k] - d.small_lo[t];
+                    if (rel < d.small_hi[t] - d.small_lo[t]) {
+                        float *sp = small + (t * kTrainSmallTexels + rel) * 3;
+                        atomicAdd(sp + 0, wt[k] * dz[3 * t + 0]);
+                        atomicAdd(sp + 1, wt[k] * dz[3 * t + 1]);
+                        atomicAdd(sp + 2, wt[k] * dz[3 * t + 2]);
+                    } else {
+                        float *gp = reinterpret_cast<float *>(d.g_texels + idx[k]);
+                        unsafeAtomicAdd(gp + 0, wt[k] * dz[3 * t + 0]);
+                        unsafeAtomicAdd(gp + 1, wt[k] * dz[3 * t + 1]);
+                        unsafeAtomicAdd(gp + 2, wt[k] * dz[3 * t + 2]);
+                    }
                 }
             }
         }
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < kMaxTextures * kTrainSmallTexels * 3; i += kBwdThreads) {
+        const uint32_t t = i / (kTrainSmallTexels * 3), j = (i / 3) % kTrainSmallTexels, c = i % 3;
+        if (t < d.n_tex && j < d.small_hi[t] - d.small_lo[t] && small[i] != 0.0f)
+            unsafeAtomicAdd(reinterpret_cast<float *>(d.g_texels + d.small_lo[t] + j) + c, small[i]);
     }
     flush<K0>(acc0, d.g_params + d.w_off[0], n0, H, lane);
 #pragma unroll
@@ -482,9 +505,9 @@ hipError_t forward_hn(const TrainDesc &d, const float *queries, uint32_t n, floa
 template <int H, int NH>
 hipError_t backward_hn(const TrainDesc &d, const float *queries, uint32_t n, const float *grad_out, hipStream_t s)
 {
-    // a few waves per CU: every wave flushes its parameter sums once
-    const unsigned grid = grid_for((n + 63u) / 64u, kTrainWaves, 512);
-    k_train_backward<H, NH><<<grid, kTrainThreads, 0, s>>>(d, queries, n, grad_out);
+    // a few workgroups per CU: each flushes its parameter and small-level sums once
+    const unsigned grid = grid_for((n + 63u) / 64u, kBwdWaves, 768);
+    k_train_backward<H, NH><<<grid, kBwdThreads, 0, s>>>(d, queries, n, grad_out);
     return hipGetLastError();
 }
 

@@ -12,6 +12,8 @@
 namespace bcf {
 
 constexpr int kTrainMaxHidden = 32;
+// texels of each pyramid's smallest levels whose gradients the backward sums in LDS
+constexpr uint32_t kTrainSmallTexels = 352;
 
 // One pyramid of continuous two-subset blocks (6-bit endpoints, 3-bit
 // indices, fixed partitions), all levels back to back.
@@ -42,6 +44,9 @@ struct TrainDesc {
     uint32_t dims[5];
     uint32_t n_layers;
     uint32_t w_off[4], b_off[4];   // float offsets of each layer's W and b in params
+    // per pyramid: its smallest levels, texels small_lo .. small_hi - 1 of the
+    // images (at most kTrainSmallTexels), summed per workgroup in LDS
+    uint32_t small_lo[kMaxTextures], small_hi[kMaxTextures];
 };
 
 hipError_t launch_train_forward(const TrainDesc &d, const float *queries, size_t n, float *out,

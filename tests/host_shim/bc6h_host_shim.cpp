@@ -17,3 +17,26 @@ extern "C" void shim_decode_blocks(const uint32_t *blocks, size_t n, int is_sign
                                                                : bcf::bc6h_texel<false>(h, t, c));
     }
 }
+
+// The same through the palette the unpack kernel uses.
+extern "C" void shim_decode_blocks_palette(const uint32_t *blocks, size_t n, int is_signed, uint16_t *out)
+{
+    for (size_t i = 0; i < n; ++i) {
+        const uint32_t *b = blocks + 4 * i;
+        bcf::Bc6hHeader h;
+        uint32_t pal[16][2];
+        if (is_signed) {
+            bcf::bc6h_header<true>(b[0], b[1], b[2], b[3], bcf::kTable, h);
+            bcf::bc6h_palette<true>(h, pal);
+        } else {
+            bcf::bc6h_header<false>(b[0], b[1], b[2], b[3], bcf::kTable, h);
+            bcf::bc6h_palette<false>(h, pal);
+        }
+        for (uint32_t t = 0; t < 16; ++t) {
+            const uint32_t j = bcf::bc6h_slot(h, t);
+            out[48 * i + 3 * t + 0] = (uint16_t)(pal[j][0] & 0xFFFFu);
+            out[48 * i + 3 * t + 1] = (uint16_t)(pal[j][0] >> 16);
+            out[48 * i + 3 * t + 2] = (uint16_t)pal[j][1];
+        }
+    }
+}

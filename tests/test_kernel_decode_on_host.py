@@ -34,13 +34,15 @@ def shim():
                        check=True, stderr=subprocess.DEVNULL)
     L = C.CDLL(OUT)
     L.shim_decode_blocks.argtypes = [C.c_void_p, C.c_size_t, C.c_int, C.c_void_p]
+    L.shim_decode_blocks_palette.argtypes = [C.c_void_p, C.c_size_t, C.c_int, C.c_void_p]
     return L
 
 
-def run(shim, blocks, signed):
+def run(shim, blocks, signed, palette=False):
     b = np.ascontiguousarray(blocks, np.uint8)
     out = np.zeros((b.shape[0], 16, 3), np.uint16)
-    shim.shim_decode_blocks(b.ctypes.data, b.shape[0], int(signed), out.ctypes.data)
+    fn = shim.shim_decode_blocks_palette if palette else shim.shim_decode_blocks
+    fn(b.ctypes.data, b.shape[0], int(signed), out.ctypes.data)
     return out
 
 
@@ -67,3 +69,13 @@ def test_single_bit_flips(shim, mode):
     blocks = np.concatenate(flips)
     for signed in (False, True):
         assert np.array_equal(run(shim, blocks, signed), oracle.decode_blocks(blocks, signed))
+
+
+@pytest.mark.parametrize("signed", [False, True])
+def test_palette_path_every_mode(shim, signed):
+    # the unpack kernel reads texels from a 16-entry palette per block
+    g = synth.rng(1200 + signed)
+    blocks = np.concatenate([synth.random_mode_blocks(60000, g), synth.reserved_blocks(2000, g),
+                             synth.bounded_blocks(20000, g), synth.bounded_blocks(20000, g, signed=True)])
+    got = run(shim, blocks, signed, palette=True)
+    assert np.array_equal(got, oracle.decode_blocks(blocks, signed))
