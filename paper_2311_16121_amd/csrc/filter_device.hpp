@@ -65,6 +65,9 @@ struct Footprint {
 
 __device__ __forceinline__ Footprint footprint(uint4 e, float uf, float vf, float lw)
 {
+    // every product and sum below is rounded as written, whichever kernel
+    // this is inlined into, so all decode kernels filter bit-identically
+#pragma clang fp contract(off)
     // copy the fields to plain integers before reinterpreting them
     const uint32_t ew = e.x, eh = e.y, masks = e.z, first = e.w;
     const float x = fmaf(uf, __builtin_bit_cast(float, ew), -0.5f);
@@ -79,11 +82,11 @@ __device__ __forceinline__ Footprint footprint(uint4 e, float uf, float vf, floa
     Footprint f;
     f.o0 = ((y0 << lw2) + 2u * y0 + x0 + first) * 8u;
     f.o1 = ((y1 << lw2) + 2u * y1 + x0 + first) * 8u;
-    const float wx1 = fx * lw, wx0 = lw - wx1;
+    const float wx1 = fx * lw, wx0 = fmaf(-fx, lw, lw);
     f.w01 = wx0 * fy;
     f.w11 = wx1 * fy;
-    f.w00 = wx0 - f.w01;
-    f.w10 = wx1 - f.w11;
+    f.w00 = fmaf(-wx0, fy, wx0);
+    f.w10 = fmaf(-wx1, fy, wx1);
     return f;
 }
 
@@ -114,6 +117,44 @@ __device__ __forceinline__ void gather(__amdgpu_buffer_rsrc_t rs, const Footprin
     const texel_pair r0 = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(f.o0 + shift), 0, 0);
     const texel_pair r1 = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(f.o1 + shift), 0, 0);
     blend(f, r0, r1, acc);
+}
+
+// A query's trilinear footprint for pyramids of one shared geometry, with its
+// 16 texel-pair loads issued (4 slots x 2 levels x 2 rows), so the frame
+// kernel can fetch the next work item before storing the current one.
+struct PendingTaps {
+    Footprint f0, f1;
+    texel_pair r[kMaxTextures][2][2];
+};
+
+__device__ __forceinline__ void fetch4_shared(__amdgpu_buffer_rsrc_t rs, const LevelLut &lut,
+                                              const float *levels_bias, uint32_t stride, float u, float v,
+                                              float s, PendingTaps &p)
+{
+    const float uf = u - floorf(u), vf = v - floorf(v);       // wrap addressing
+    const LevelSel ls = select_levels(s, levels_bias[1], __builtin_bit_cast(uint32_t, levels_bias[0]));
+    p.f0 = footprint(lut.e[0][ls.l0], uf, vf, 1.0f - ls.lam);
+    p.f1 = footprint(lut.e[0][ls.l1], uf, vf, ls.lam);
+#pragma unroll
+    for (int t = 0; t < kMaxTextures; ++t) {
+        const uint32_t sh = (uint32_t)t * stride;
+        p.r[t][0][0] = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(p.f0.o0 + sh), 0, 0);
+        p.r[t][0][1] = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(p.f0.o1 + sh), 0, 0);
+        p.r[t][1][0] = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(p.f1.o0 + sh), 0, 0);
+        p.r[t][1][1] = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(p.f1.o1 + sh), 0, 0);
+    }
+}
+
+// the sums of filter4<true> from fetched taps
+__device__ __forceinline__ void filter_pending(const PendingTaps &p, float z[12])
+{
+#pragma unroll
+    for (int i = 0; i < 12; ++i) z[i] = 0.0f;
+#pragma unroll
+    for (int t = 0; t < kMaxTextures; ++t) {
+        blend(p.f0, p.r[t][0][0], p.r[t][0][1], z + 3 * t);
+        blend(p.f1, p.r[t][1][0], p.r[t][1][1], z + 3 * t);
+    }
 }
 
 // z[3t + c] = T_t(u, v, s) channel c for the four pyramid slots (slots past

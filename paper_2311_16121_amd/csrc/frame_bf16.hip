@@ -3,10 +3,10 @@
 
 namespace bcf {
 
-hipError_t launch_frame_bf16(const FrameArgs &a, const MlpShape &sh, bool shared, unsigned grid, hipStream_t s)
+hipError_t launch_frame_bf16(const FrameArgs &a, const MlpShape &sh, bool shared, hipStream_t s)
 {
-    return shared ? launch_frame_kind<MLP_MFMA_BF16, 16, true>(a, sh, grid, s)
-                  : launch_frame_kind<MLP_MFMA_BF16, 16, false>(a, sh, grid, s);
+    return shared ? launch_frame_kind<MLP_MFMA_BF16, 16, true>(a, sh, s)
+                  : launch_frame_kind<MLP_MFMA_BF16, 16, false>(a, sh, s);
 }
 
 }  // namespace bcf

@@ -25,9 +25,6 @@ typedef uint32_t uint4_t __attribute__((ext_vector_type(4)));
 
 constexpr int kFrameThreads = 256;
 constexpr int kFrameWaves = kFrameThreads / 64;
-// 16-byte output chunks per lane of a 64-query item (64 rows of <= 16 floats)
-constexpr int kTileChunks = 64 * kMaxOut / 4 / 64;
-
 // a wave's 64 feature vectors (4 x float4 each) fit its output stage
 static_assert(64 * 4 <= 64 * kMaxOut / 4, "feature vectors must fit the output stage");
 
@@ -43,26 +40,50 @@ struct FrameArgs {
     uint32_t out_dim;
     float *absmax;                         // k_calibrate: per-layer largest |input|
     // 2D work items: with grid_w > 0 the queries are image rows of grid_w and
-    // a wave takes a tile of 2^tile_log2 columns by 64 / 2^tile_log2 rows
-    // (lane = row * width + column); with 0, 64 consecutive queries.
-    // rows_b128: grid_w * out_dim is a multiple of 4 (16-byte rows)
-    uint32_t grid_w, tiles_x, n_items, rows_b128, tile_log2;
+    // a wave takes a tile of kTileW columns by kTileH rows (lane = row *
+    // kTileW + column); with 0, 64 consecutive queries.
+    // wide: every output row this launch writes starts on a 16-byte boundary
+    // and n * out_dim is a multiple of 4, so items store 16-byte chunks
+    uint32_t grid_w, tiles_x, n_items, wide;
+    // tiled work: tiles_y rows of tiles; bands = kXcds splits the tile
+    // columns into one band per XCD, 1 keeps a single band
+    uint32_t tiles_y, bands;
 };
 
-// The grid is a multiple of the 8 XCDs (workgroups are dispatched to them
-// round-robin). Work items go round-robin over all waves, so the waves on the
-// chip at any moment work on neighbouring items (measured faster than giving
-// each XCD its own band: the bands differ in how often they miss L2).
+// Work-item tiles for queries declared as an image: 16 x 4.
+constexpr uint32_t kTileLog2 = 4, kTileW = 1u << kTileLog2, kTileH = 64u >> kTileLog2;
+
+// The grid is a multiple of the 8 XCDs, to which workgroups are dispatched
+// round-robin (workgroup b runs on XCD b % 8), and no larger than what is
+// resident at once, so all waves sweep the image together. Tiled work gives
+// each XCD a band of tile columns, walked in row order by that XCD's waves
+// in turn: the tiles in flight on an XCD at any moment are a few rows of its
+// band, whose vertical and horizontal neighbours -- sharing texels -- sit in
+// the same XCD's L2. Linear work (and images too narrow for bands) goes
+// round-robin over all waves.
 constexpr uint32_t kXcds = 8;
+
+// A wave's share of the work: items first, first + step, ... below end of a
+// band of bw tile columns starting at column c0 (linear work: bw = 1, and
+// the item's row of "tiles" is the item).
+struct WaveWork {
+    uint32_t first, end, step, c0, bw;
+};
+
+__device__ __forceinline__ WaveWork wave_work(const FrameArgs &a, uint32_t wv)
+{
+    if (a.bands == kXcds) {
+        const uint32_t x = blockIdx.x % kXcds;
+        const uint32_t c0 = x * a.tiles_x / kXcds, c1 = (x + 1) * a.tiles_x / kXcds;
+        return WaveWork{(blockIdx.x / kXcds) * kFrameWaves + wv, (c1 - c0) * a.tiles_y,
+                        (gridDim.x / kXcds) * kFrameWaves, c0, c1 - c0};
+    }
+    return WaveWork{blockIdx.x * kFrameWaves + wv, a.n_items, gridDim.x * kFrameWaves, 0, a.grid_w ? a.tiles_x : 1u};
+}
 
 struct ItemRange {
     uint32_t first, end, step;
 };
-
-__device__ __forceinline__ ItemRange wave_items(uint32_t n_items, uint32_t wv)
-{
-    return ItemRange{blockIdx.x * kFrameWaves + wv, n_items, gridDim.x * kFrameWaves};
-}
 
 struct Query {
     float u, v, s;
@@ -181,14 +202,24 @@ __device__ __forceinline__ void mlp_stage(const float z[12], const uint8_t *wbas
 #pragma unroll
         for (int grp = 0; grp < 4; ++grp) fin[grp] = feats[16 * grp + qi][g];
         wave_lds_sync();                      // feats and st share the wave's LDS
+        // lane (g, qi) holds outputs 4g .. 4g + 3 of its query; those past
+        // out_dim go to the stage's last float, which 64 rows of fewer than
+        // kMaxOut outputs never use (a select, not a branch per output)
+        constexpr uint32_t kSpare = 64 * kMaxOut - 1;
+        float f[4][4];
+#pragma unroll
+        for (int grp = 0; grp < 4; ++grp)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) f[grp][i] = fin[grp][i];
+        float4_t o[4];
+        mlp.template run_groups<4>(f, o);
 #pragma unroll
         for (int grp = 0; grp < 4; ++grp) {
-            const float f[4] = {fin[grp][0], fin[grp][1], fin[grp][2], fin[grp][3]};
-            const float4_t o4 = mlp.run(f);
+            const float4_t o4 = o[grp];
             const uint32_t row = (16 * grp + qi) * out_dim;
 #pragma unroll
             for (int j = 0; j < 4; ++j)
-                if (4 * g + j < out_dim) st[row + 4 * g + j] = o4[j];
+                st[4 * g + j < out_dim ? row + 4 * g + j : kSpare] = o4[j];
         }
     }
     wave_lds_sync();
@@ -226,6 +257,72 @@ __device__ __forceinline__ void store_run(const float4_t *stage, __amdgpu_buffer
     }
 }
 
+// Stores of one work item: always 16 / V buffer stores of V floats per lane
+// (V = 4 when FrameArgs::wide, else 1) and no branches around them. An item's
+// output is a set of runs of contiguous floats: one run of 64 * out_dim for
+// linear items, one of kTileW * out_dim per tile row for tiled items. The
+// lanes of a run take its V-float chunks in turn; a chunk with nowhere to go
+// (past the run, the image's right edge or the output's end) is sent to
+// `oob`, the first byte past the output buffer, which the buffer range check
+// drops. Stores count in the same in-order counter as loads; a fixed count
+// lets the compiler wait for a load issued before these stores without
+// waiting for the stores themselves.
+template <int V>
+__device__ __forceinline__ void store_item(const FrameArgs &a, uint32_t oob, const float *st,
+                                           __amdgpu_buffer_rsrc_t ro, uint32_t it, uint32_t row0, uint32_t col0,
+                                           uint32_t lane)
+{
+    typedef float vec_t __attribute__((ext_vector_type(V)));
+    const uint32_t n_out = a.n * a.out_dim;
+    uint32_t e0, step, k0, base, lim;
+    if (!a.grid_w) {
+        base = it * 64u * a.out_dim;
+        lim = min(64u * a.out_dim, n_out - min(base, n_out));
+        e0 = V * lane;
+        step = 64u * V;
+        k0 = 0;
+    } else {
+        const uint32_t r = lane >> kTileLog2;
+        base = ((row0 + r) * a.grid_w + col0) * a.out_dim;
+        lim = min(kTileW, a.grid_w - col0) * a.out_dim;
+        lim = min(lim, n_out - min(base, n_out));
+        e0 = V * (lane & (kTileW - 1u));
+        step = kTileW * V;
+        k0 = r * kTileW * a.out_dim;
+    }
+#pragma unroll
+    for (int m = 0; m < 16 / V; ++m) {
+        const uint32_t e = e0 + step * m;
+        const vec_t v = *reinterpret_cast<const vec_t *>(st + k0 + e);
+        const int off = (int)(e < lim ? (base + e) * 4u : oob);
+        if constexpr (V == 4)
+            __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(uint4_t, v), ro, off, 0, 0);
+        else
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), ro, off, 0, 0);
+    }
+}
+
+// 16 / V stores past the output's end: the loop's entry then has the same
+// stores outstanding as its back edge.
+template <int V>
+__device__ __forceinline__ void store_dummies(__amdgpu_buffer_rsrc_t ro, uint32_t oob)
+{
+#pragma unroll
+    for (int m = 0; m < 16 / V; ++m) {
+        uint32_t o = oob;
+        asm volatile("" : "+v"(o));           // separate stores, not merged into wider ones
+        if constexpr (V == 4)
+            __builtin_amdgcn_raw_buffer_store_b128(uint4_t{0, 0, 0, 0}, ro, (int)o, 0, 0);
+        else
+            __builtin_amdgcn_raw_buffer_store_b32(0u, ro, (int)o, 0, 0);
+    }
+}
+
+template <int V>
+struct Width {
+    static constexpr int value = V;
+};
+
 template <MlpKind K, int H, int NH, int C, bool SHARED>
 __global__ void __launch_bounds__(kFrameThreads) k_frame(FrameArgs a)
 {
@@ -246,72 +343,72 @@ __global__ void __launch_bounds__(kFrameThreads) k_frame(FrameArgs a)
     float *st = reinterpret_cast<float *>(&stage[wv][0]);
     float4_t (*feats)[4] = reinterpret_cast<float4_t (*)[4]>(&stage[wv][0]);
 
-    // Full tiles store each row of tile_w * out_dim floats as 16-byte chunks;
-    // chunk k = lane + 64 m sits at tile_off[m] bytes from the tile's first
-    // output (all-ones: no such chunk).
-    const uint32_t tile_w = 1u << a.tile_log2, tile_h = 64u >> a.tile_log2;
-    uint32_t tile_off[kTileChunks];
-    {
-        const uint32_t per_row = (tile_w * a.out_dim) >> 2;
-#pragma unroll
-        for (int m = 0; m < kTileChunks; ++m) {
-            const uint32_t k = lane + 64u * m, r = k / per_row, c = k - r * per_row;
-            tile_off[m] = k < 16u * a.out_dim ? r * a.grid_w * a.out_dim * 4u + 16u * c : 0xFFFFFFFFu;
-        }
-    }
-    // this lane's query of item `it` (and the item's tile origin); lanes
-    // outside the image or past n read zeros (buffer range check) and their
-    // rows are not stored
-    auto query_of = [&](uint32_t it, uint32_t &row0, uint32_t &col0) -> uint32_t {
+    const uint32_t oob = a.n * a.out_dim * 4u;
+    const WaveWork w = wave_work(a, wv);
+    if (w.first >= w.end) return;
+    // Item k of this wave's band: tile row t0 = k / bw, column c0 + k % bw.
+    // Sets `it` (the linear item, = t0) and the tile's origin, and returns this
+    // lane's query; lanes outside the image or past n read zeros (buffer
+    // range check) and their rows are not stored.
+    auto query_of = [&](uint32_t k, uint32_t &it, uint32_t &row0, uint32_t &col0) -> uint32_t {
+        const uint32_t t0 = k / w.bw;
+        it = t0;
         if (!a.grid_w) {
             row0 = col0 = 0;
-            return it * 64 + lane;
+            return t0 * 64 + lane;
         }
-        row0 = (it / a.tiles_x) * tile_h;
-        col0 = (it % a.tiles_x) * tile_w;
-        const uint32_t col = col0 + (lane & (tile_w - 1u));
-        const uint32_t q = (row0 + (lane >> a.tile_log2)) * a.grid_w + col;
+        row0 = t0 * kTileH;
+        col0 = (w.c0 + (k - t0 * w.bw)) * kTileW;
+        const uint32_t col = col0 + (lane & (kTileW - 1u));
+        const uint32_t q = (row0 + (lane >> kTileLog2)) * a.grid_w + col;
         return col < a.grid_w && q < a.n ? q : a.n;
     };
-    const ItemRange items = wave_items(a.n_items, wv);
-    uint32_t row0, col0;
-    // the next item's query is loaded while this item's texels are fetched
-    Query next = load_query(rq, query_of(items.first < items.end ? items.first : 0, row0, col0));
-    for (uint32_t it = items.first; it < items.end; it += items.step) {
-        query_of(it, row0, col0);
-        const Query qq = next;
-        if (it + items.step < items.end) {
-            uint32_t r, c;
-            next = load_query(rq, query_of(it + items.step, r, c));
-        }
-        decode_wave<K, H, NH, C, SHARED>(qq, rs, lut, a.levels_bias, a.stride, a.ws, a.lay, mlp, feats, st,
-                                         a.out_dim, lane);
-        // Staged rows: lane L's outputs at st[L * out_dim ...]. A tile row or a
-        // run of 64 consecutive queries is one contiguous span of out.
-        if (!a.grid_w) {
-            store_run(stage[wv], ro, it, a.n, a.out_dim, lane);
+    const ItemRange items{w.first, w.end, w.step};
+    auto run = [&](auto width) {
+        constexpr int V = decltype(width)::value;
+        uint32_t it, row0, col0, i_, r_, c_;
+        if (SHARED) {
+            // Per item: blend its texels, run the MLP, issue the next item's
+            // texel loads and the query after that, then store -- so the
+            // wait for the next texels never includes these stores. The loop
+            // is entered the way it repeats (texel loads, a query load, the
+            // stores), and the last item fetches its first item again, so
+            // every path into the loop's top has the same loads and stores
+            // outstanding.
+            auto clamp_item = [&](uint32_t k) { return k < items.end ? k : items.first; };
+            const Query q0 = load_query(rq, query_of(items.first, i_, r_, c_));
+            PendingTaps taps;
+            fetch4_shared(rs, lut, a.levels_bias, a.stride, q0.u, q0.v, q0.s, taps);
+            Query qnext = load_query(rq, query_of(clamp_item(items.first + items.step), i_, r_, c_));
+            store_dummies<V>(ro, oob);
+            for (uint32_t k = items.first; k < items.end; k += items.step) {
+                query_of(k, it, row0, col0);
+                float z[12];
+                filter_pending(taps, z);
+                mlp_stage<K, H, NH, C>(z, a.ws, a.lay, mlp, feats, st, a.out_dim, lane);
+                fetch4_shared(rs, lut, a.levels_bias, a.stride, qnext.u, qnext.v, qnext.s, taps);
+                qnext = load_query(rq, query_of(clamp_item(k + 2 * items.step), i_, r_, c_));
+                store_item<V>(a, oob, st, ro, it, row0, col0, lane);
+                wave_lds_sync();
+            }
         } else {
-            const bool full = col0 + tile_w <= a.grid_w && (row0 + tile_h - 1u) * a.grid_w + col0 + tile_w <= a.n;
-            if (full && a.rows_b128) {
-                const uint32_t base = (row0 * a.grid_w + col0) * a.out_dim * 4u;
-#pragma unroll
-                for (int m = 0; m < kTileChunks; ++m)
-                    if (tile_off[m] != 0xFFFFFFFFu)
-                        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(uint4_t, stage[wv][lane + 64 * m]),
-                                                               ro, (int)(base + tile_off[m]), 0, 0);
-            } else {                                   // an edge tile
-                for (uint32_t k = lane; k < 64u * a.out_dim; k += 64) {
-                    const uint32_t src = k / a.out_dim, j = k - src * a.out_dim;
-                    const uint32_t col = col0 + (src & (tile_w - 1u));
-                    const uint32_t qq2 = (row0 + (src >> a.tile_log2)) * a.grid_w + col;
-                    if (col < a.grid_w && qq2 < a.n)
-                        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, st[k]), ro,
-                                                              (int)((qq2 * a.out_dim + j) * 4u), 0, 0);
-                }
+            // the next item's query is loaded while this item's texels are fetched
+            Query next = load_query(rq, query_of(items.first, i_, r_, c_));
+            for (uint32_t k = items.first; k < items.end; k += items.step) {
+                query_of(k, it, row0, col0);
+                const Query qq = next;
+                if (k + items.step < items.end) next = load_query(rq, query_of(k + items.step, i_, r_, c_));
+                decode_wave<K, H, NH, C, SHARED>(qq, rs, lut, a.levels_bias, a.stride, a.ws, a.lay, mlp, feats,
+                                                 st, a.out_dim, lane);
+                store_item<V>(a, oob, st, ro, it, row0, col0, lane);
+                wave_lds_sync();
             }
         }
-        wave_lds_sync();
-    }
+    };
+    if (a.wide)
+        run(Width<4>());
+    else
+        run(Width<1>());
 }
 
 // The plain fp32 decode that records each layer's largest input magnitude
@@ -399,7 +496,7 @@ __global__ void __launch_bounds__(kFrameThreads) k_batch(BatchArgs a)
 
     ItemRange items;
     if (a.interleave) {
-        items = wave_items(total, wv);
+        items = ItemRange{blockIdx.x * kFrameWaves + wv, total, gridDim.x * kFrameWaves};
     } else {
         // contiguous: the XCD's band split into one range per wave
         const uint32_t xcd = blockIdx.x % kXcds, local = blockIdx.x / kXcds;
@@ -474,12 +571,39 @@ hipError_t launch_batch_kind(const BatchArgs &a, const MlpShape &sh, unsigned gr
     return hipErrorInvalidValue;
 }
 
+// Workgroups of `kernel` resident at once on the current device (cached per
+// kernel and device).
+template <typename F>
+unsigned resident_workgroups(F kernel)
+{
+    static int cache[16];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return 0;
+    if (dev < 16 && cache[dev] > 0) return (unsigned)cache[dev];
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kFrameThreads, 0) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    const int r = std::max(per_cu, 1) * std::max(cus, 1);
+    if (dev < 16) cache[dev] = r;
+    return (unsigned)r;
+}
+
+// one workgroup per kFrameWaves items, at most the resident count, a multiple of the XCDs
+inline unsigned frame_launch_grid(uint32_t n_items, unsigned resident)
+{
+    const unsigned want = (n_items + kFrameWaves - 1) / kFrameWaves;
+    const unsigned cap = std::max(kXcds, resident / kXcds * kXcds);
+    return std::min(std::max(kXcds, (want + kXcds - 1) / kXcds * kXcds), cap);
+}
+
 template <MlpKind K, int C, bool SH>
-hipError_t launch_frame_kind(const FrameArgs &a, const MlpShape &sh, unsigned grid, hipStream_t s)
+hipError_t launch_frame_kind(const FrameArgs &a, const MlpShape &sh, hipStream_t s)
 {
 #define BCF_CASE(H, NH)                                                                       \
     if (sh.hidden == H && sh.n_hidden == NH) {                                               \
-        k_frame<K, H, NH, C, SH><<<grid, kFrameThreads, 0, s>>>(a);                           \
+        const auto kern = k_frame<K, H, NH, C, SH>;                                           \
+        kern<<<frame_launch_grid(a.n_items, resident_workgroups(kern)), kFrameThreads, 0, s>>>(a); \
         return hipGetLastError();                                                             \
     }
     BCF_CASE(16, 1) BCF_CASE(16, 2) BCF_CASE(16, 3)
@@ -490,12 +614,11 @@ hipError_t launch_frame_kind(const FrameArgs &a, const MlpShape &sh, unsigned gr
 }
 
 // per-precision entry points (frame_<precision>.hip)
-hipError_t launch_frame_f32(const FrameArgs &a, const MlpShape &sh, bool shared, unsigned grid, hipStream_t s);
-hipError_t launch_frame_f16(const FrameArgs &a, const MlpShape &sh, bool shared, unsigned grid, hipStream_t s);
-hipError_t launch_frame_bf16(const FrameArgs &a, const MlpShape &sh, bool shared, unsigned grid, hipStream_t s);
-hipError_t launch_frame_fp8(const FrameArgs &a, const MlpShape &sh, bool shared, unsigned grid, hipStream_t s);
-hipError_t launch_frame_f32_mfma(const FrameArgs &a, const MlpShape &sh, bool shared, unsigned grid,
-                                 hipStream_t s);
+hipError_t launch_frame_f32(const FrameArgs &a, const MlpShape &sh, bool shared, hipStream_t s);
+hipError_t launch_frame_f16(const FrameArgs &a, const MlpShape &sh, bool shared, hipStream_t s);
+hipError_t launch_frame_bf16(const FrameArgs &a, const MlpShape &sh, bool shared, hipStream_t s);
+hipError_t launch_frame_fp8(const FrameArgs &a, const MlpShape &sh, bool shared, hipStream_t s);
+hipError_t launch_frame_f32_mfma(const FrameArgs &a, const MlpShape &sh, bool shared, hipStream_t s);
 hipError_t launch_calibrate_kernel(const FrameArgs &a, const MlpShape &sh, bool shared, unsigned grid,
                                    hipStream_t s);
 hipError_t launch_batch_f16(const BatchArgs &a, const MlpShape &sh, unsigned grid, hipStream_t s);

@@ -351,10 +351,7 @@ static FrameArgs frame_args(const MaterialDesc &m, const WsLayout &lay, const vo
     return a;
 }
 
-// Tile width (log2) for queries declared as an image: 16 x 4 tiles.
-constexpr uint32_t kTileLog2 = 4;
-
-// Persistent waves: at most 16 workgroups of 4 waves per CU, a multiple of the XCD count.
+// The calibration's grid: at most 16 workgroups of 4 waves per CU, a multiple of the XCD count.
 static unsigned frame_grid(uint32_t items)
 {
     const uint32_t blocks = std::min<uint32_t>((items + kFrameWaves - 1) / kFrameWaves, 256u * 16u);
@@ -367,18 +364,17 @@ hipError_t launch_filter_mlp(const MaterialDesc &m, const MlpShape &sh, MlpKind 
 {
     bool shared;
     FrameArgs a = frame_args(m, lay, ws, sh.out, &shared);
-    auto launch = [&](unsigned grid) -> hipError_t {
+    auto launch = [&]() -> hipError_t {
         switch (kind) {
-        case MLP_VALU_F32: return launch_frame_f32(a, sh, shared, grid, s);
-        case MLP_MFMA_F16: return launch_frame_f16(a, sh, shared, grid, s);
-        case MLP_MFMA_BF16: return launch_frame_bf16(a, sh, shared, grid, s);
-        case MLP_MFMA_FP8: return launch_frame_fp8(a, sh, shared, grid, s);
-        case MLP_MFMA_F32: return launch_frame_f32_mfma(a, sh, shared, grid, s);
+        case MLP_VALU_F32: return launch_frame_f32(a, sh, shared, s);
+        case MLP_MFMA_F16: return launch_frame_f16(a, sh, shared, s);
+        case MLP_MFMA_BF16: return launch_frame_bf16(a, sh, shared, s);
+        case MLP_MFMA_FP8: return launch_frame_fp8(a, sh, shared, s);
+        case MLP_MFMA_F32: return launch_frame_f32_mfma(a, sh, shared, s);
         default: return hipErrorInvalidValue;
         }
     };
-    const uint32_t tile_w = 1u << kTileLog2, tile_h = 64u >> kTileLog2;
-    if (grid_width >= tile_w && grid_width <= n && n <= kMaxQueriesPerLaunch) {
+    if (grid_width >= kTileW && grid_width <= n && n <= kMaxQueriesPerLaunch) {
         // an image of grid_width columns: tiles of several rows, so a wave's
         // queries read overlapping texels in both directions
         const uint32_t rows = (uint32_t)((n + grid_width - 1) / grid_width);
@@ -386,11 +382,12 @@ hipError_t launch_filter_mlp(const MaterialDesc &m, const MlpShape &sh, MlpKind 
         a.out = out;
         a.n = (uint32_t)n;
         a.grid_w = grid_width;
-        a.tile_log2 = kTileLog2;
-        a.tiles_x = (grid_width + tile_w - 1) / tile_w;
-        a.n_items = a.tiles_x * ((rows + tile_h - 1) / tile_h);
-        a.rows_b128 = (grid_width * sh.out) % 4 == 0;
-        return launch(frame_grid(a.n_items));
+        a.tiles_x = (grid_width + kTileW - 1) / kTileW;
+        a.tiles_y = (rows + kTileH - 1) / kTileH;
+        a.n_items = a.tiles_x * a.tiles_y;
+        a.bands = a.tiles_x >= 2 * kXcds ? kXcds : 1;        // at least two tile columns per band
+        a.wide = (grid_width * sh.out) % 4 == 0 && (a.n * sh.out) % 4 == 0 && ((uintptr_t)out & 15) == 0;
+        return launch();
     }
     // one launch covers at most kMaxQueriesPerLaunch queries (32-bit buffer offsets)
     for (size_t first = 0; first < n; first += kMaxQueriesPerLaunch) {
@@ -399,7 +396,8 @@ hipError_t launch_filter_mlp(const MaterialDesc &m, const MlpShape &sh, MlpKind 
         a.out = out + sh.out * first;
         a.n = cnt;
         a.n_items = (cnt + 63) / 64;
-        const hipError_t e = launch(frame_grid(a.n_items));
+        a.wide = (cnt * sh.out) % 4 == 0 && ((uintptr_t)a.out & 15) == 0;
+        const hipError_t e = launch();
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

@@ -285,9 +285,10 @@ def test_unpack_then_decode_unpacked_equals_decode(bcf):
 
 @pytest.mark.parametrize("dims", [(12, 32, 32, 10), (12, 16, 9)])
 def test_grid_width_does_not_change_results(bcf, dims):
-    # 8x8 tiles over images with ragged right and bottom edges, widths that are
-    # and are not multiples of 8, rows whose byte length is and is not a
-    # multiple of 16, against the plain run of consecutive queries
+    # 16x4 tiles over images with ragged right and bottom edges, widths that
+    # are and are not multiples of 16 (and narrower than a tile), rows whose
+    # byte length is and is not a multiple of 16 (16-byte and 4-byte stores),
+    # against the plain run of consecutive queries
     texs, sizes, lv, params, bias, host = make(64, 7, dims, "B", seed=31)
     mat = bcf.Material.from_host(texs, sizes, lv, dims, params, bias)
     g = synth.rng(32)
@@ -300,3 +301,27 @@ def test_grid_width_does_not_change_results(bcf, dims):
             flat = bcf.decode(mat, ws, qd, prec).cpu().numpy()
             tiled = bcf.decode(mat, ws, qd, prec, grid_width=width).cpu().numpy()
             assert np.array_equal(flat.view(np.uint32), tiled.view(np.uint32)), (n, width, p)
+
+
+@pytest.mark.parametrize("dims", [(12, 32, 32, 10), (12, 16, 9)])
+def test_output_view_writes_only_its_rows(bcf, dims):
+    # `out` a view into a larger NaN-filled buffer, at offsets that keep and
+    # that break 16-byte alignment: the decode writes exactly its own rows
+    # (the dropped out-of-range stores of partial work items never land past
+    # the view) and equals the decode into a fresh buffer
+    texs, sizes, lv, params, bias, host = make(64, 7, dims, "B", seed=33)
+    mat = bcf.Material.from_host(texs, sizes, lv, dims, params, bias)
+    g = synth.rng(34)
+    c = dims[-1]
+    for n, width, lead in ((4096, 64, 4), (53 * 37 + 17, 53, 1), (1000, 0, 3), (1000, 0, 4), (1001, 0, 2),
+                           (999, 999, 8)):
+        q = dev(synth.uniform_queries(n, g, 6.0))
+        for p in ("FP32", "FP16"):
+            prec = bcf.Precision[p]
+            ws = bcf.prepare(mat, prec)
+            ref = bcf.decode(mat, ws, q, prec, grid_width=width).cpu().numpy()
+            big = torch.full((lead + n + 70, c), float("nan"), device="cuda")
+            bcf.decode(mat, ws, q, prec, grid_width=width, out=big[lead: lead + n])
+            got = big.cpu().numpy()
+            assert np.isnan(got[:lead]).all() and np.isnan(got[lead + n:]).all(), (n, width, lead, p)
+            assert np.array_equal(got[lead: lead + n].view(np.uint32), ref.view(np.uint32)), (n, width, lead, p)
