@@ -54,8 +54,8 @@ struct FrameArgs {
 constexpr uint32_t kTileLog2 = 4, kTileW = 1u << kTileLog2, kTileH = 64u >> kTileLog2;
 
 // The grid is a multiple of the 8 XCDs, to which workgroups are dispatched
-// round-robin (workgroup b runs on XCD b % 8), and no larger than what is
-// resident at once, so all waves sweep the image together. Tiled work gives
+// round-robin (workgroup b runs on XCD b % 8), and a small multiple of what
+// is resident at once, so the waves sweep the image nearly together. Tiled work gives
 // each XCD a band of tile columns, walked in row order by that XCD's waves
 // in turn: the tiles in flight on an XCD at any moment are a few rows of its
 // band, whose vertical and horizontal neighbours -- sharing texels -- sit in
@@ -589,21 +589,28 @@ unsigned resident_workgroups(F kernel)
     return (unsigned)r;
 }
 
-// one workgroup per kFrameWaves items, at most the resident count, a multiple of the XCDs
-inline unsigned frame_launch_grid(uint32_t n_items, unsigned resident)
+// One workgroup per kFrameWaves items, at most `cap`, a multiple of the XCDs.
+// The cap is a small multiple of the workgroups resident at once: twice for
+// the MFMA kernels, four times for the fp32 vector-ALU kernel (measured on
+// the frame benchmark: the MFMA kernels run fastest when their waves sweep
+// the image nearly together, the ALU-bound one with more waves queued behind
+// the resident ones to fill the tail).
+inline unsigned frame_launch_grid(uint32_t n_items, unsigned cap)
 {
     const unsigned want = (n_items + kFrameWaves - 1) / kFrameWaves;
-    const unsigned cap = std::max(kXcds, resident / kXcds * kXcds);
+    cap = std::max(kXcds, cap / kXcds * kXcds);
     return std::min(std::max(kXcds, (want + kXcds - 1) / kXcds * kXcds), cap);
 }
 
 template <MlpKind K, int C, bool SH>
 hipError_t launch_frame_kind(const FrameArgs &a, const MlpShape &sh, hipStream_t s)
 {
+    constexpr unsigned kOversub = K == MLP_VALU_F32 ? 4 : 2;
 #define BCF_CASE(H, NH)                                                                       \
     if (sh.hidden == H && sh.n_hidden == NH) {                                               \
         const auto kern = k_frame<K, H, NH, C, SH>;                                           \
-        kern<<<frame_launch_grid(a.n_items, resident_workgroups(kern)), kFrameThreads, 0, s>>>(a); \
+        const unsigned res = resident_workgroups(kern);                                      \
+        kern<<<frame_launch_grid(a.n_items, res ? kOversub * res : 4096u), kFrameThreads, 0, s>>>(a); \
         return hipGetLastError();                                                             \
     }
     BCF_CASE(16, 1) BCF_CASE(16, 2) BCF_CASE(16, 3)
