@@ -48,6 +48,10 @@ SHAPES = [
 ]
 
 
+# every material's pyramids share one geometry: the pipelined batch loop
+SHARED_SHAPES = [sh for sh in SHAPES if len(set(map(str, sh[0]))) == 1 and len(set(sh[1])) == 1]
+
+
 def make_batch(bcf, shapes=SHAPES, seed=61):
     g = synth.rng(seed)
     host, mats, qs = [], [], []
@@ -63,9 +67,11 @@ def make_batch(bcf, shapes=SHAPES, seed=61):
     return host, mats, qs, offsets
 
 
+@pytest.mark.parametrize("shared_only", [False, True])
 @pytest.mark.parametrize("precision", ["FP16", "FP32"])
-def test_batch_equals_single_material_decodes(bcf, precision):
-    host, mats, qs, offsets = make_batch(bcf)
+def test_batch_equals_single_material_decodes(bcf, precision, shared_only):
+    shapes = SHARED_SHAPES if shared_only else SHAPES
+    host, mats, qs, offsets = make_batch(bcf, shapes)
     prec = bcf.Precision[precision]
     batch = bcf.Batch(mats, prec)
     batch.unpack()
@@ -80,7 +86,7 @@ def test_batch_equals_single_material_decodes(bcf, precision):
         assert np.array_equal(got.view(np.uint32), ref.view(np.uint32)), k
     # and sampled rows against the oracle
     bar = 1e-5 if precision == "FP32" else 2e-3
-    for k in (0, 2, 3, 5):
+    for k in ((0, 2, 4) if shared_only else (0, 2, 3, 5)):
         pick = np.unique(np.linspace(0, len(qs[k]) - 1, 300).astype(int))
         ref = oracle.decode(host[k], qs[k][pick])
         err = np.abs(out[offsets[k] + pick] - ref).max()
@@ -117,8 +123,9 @@ def test_batch_offsets_are_clamped_and_uncovered_rows_untouched(bcf):
     assert np.array_equal(o[4600:].view(np.uint32), single(2, 4600, 5000).view(np.uint32))
 
 
-def test_batch_plans_agree_and_tuner_returns_one(bcf):
-    host, mats, qs, offsets = make_batch(bcf, seed=64)
+@pytest.mark.parametrize("shared_only", [False, True])
+def test_batch_plans_agree_and_tuner_returns_one(bcf, shared_only):
+    host, mats, qs, offsets = make_batch(bcf, SHARED_SHAPES if shared_only else SHAPES, seed=64)
     batch = bcf.Batch(mats, bcf.Precision.FP16)
     batch.unpack()
     q_all, offs = dev(np.concatenate(qs)), dev(offsets)
