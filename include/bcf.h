@@ -117,8 +117,8 @@ bcf_status bcf_prepare(const bcf_material *m, bcf_precision p, void *ws,
  * eq. (9) before the per-texture bias. grid_width > 0 declares that the
  * queries are a row-major image of that many columns (a frame in scanline
  * order; the last row may be partial), which lets the decoder walk it in
- * square tiles whose queries share texels; 0 means no 2D structure. Results
- * do not depend on grid_width.
+ * small 2D tiles whose queries share texels; 0 means no 2D structure.
+ * Results do not depend on grid_width.
  * n == 0 is a no-op. out must not overlap queries, ws or the material.
  * Non-finite query components produce unspecified values but never an
  * out-of-bounds access. Same as bcf_unpack followed by bcf_decode_unpacked

@@ -20,13 +20,18 @@ typedef uint32_t uint4_t __attribute__((ext_vector_type(4)));
 //  * plain fp32: in the lane, with wave-uniform (scalar) weight operands;
 //  * MFMA: the wave's 64 feature vectors go through LDS into the operand
 //    layout of mlp_device.hpp, four groups of 16 queries per wave.
-// Outputs are staged in LDS so each wave writes its 64 rows as contiguous
-// 16-byte stores.
+// Outputs are staged in LDS so each wave writes its 64 rows with coalesced
+// buffer stores.
 
 constexpr int kFrameThreads = 256;
 constexpr int kFrameWaves = kFrameThreads / 64;
 // a wave's 64 feature vectors (4 x float4 each) fit its output stage
 static_assert(64 * 4 <= 64 * kMaxOut / 4, "feature vectors must fit the output stage");
+
+// Cache policy of the output stores: non-temporal (streamed). The kernels
+// never read their outputs back; on the frame benchmark the decode runs about
+// a quarter faster with its output stream marked so.
+constexpr int kStoreNT = 2;   // the buffer intrinsics' cache-policy bit for "nt"
 
 struct FrameArgs {
     LevelLut lut;
@@ -247,13 +252,13 @@ __device__ __forceinline__ void store_run(const float4_t *stage, __amdgpu_buffer
     if (it * 64 + 64 <= n) {
         for (uint32_t k = lane; k < 16 * out_dim; k += 64)
             __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(uint4_t, stage[k]), ro, (int)(base + 16u * k),
-                                                   0, 0);
+                                                   0, kStoreNT);
     } else {
         const float *st = reinterpret_cast<const float *>(stage);
         const uint32_t floats = (n - it * 64) * out_dim;
         for (uint32_t k = lane; k < floats; k += 64)
             __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, st[k]), ro, (int)(base + 4u * k), 0,
-                                                  0);
+                                                  kStoreNT);
     }
 }
 
@@ -296,9 +301,9 @@ __device__ __forceinline__ void store_item(const FrameArgs &a, uint32_t oob, con
         const vec_t v = *reinterpret_cast<const vec_t *>(st + k0 + e);
         const int off = (int)(e < lim ? (base + e) * 4u : oob);
         if constexpr (V == 4)
-            __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(uint4_t, v), ro, off, 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(uint4_t, v), ro, off, 0, kStoreNT);
         else
-            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), ro, off, 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), ro, off, 0, kStoreNT);
     }
 }
 
@@ -312,9 +317,9 @@ __device__ __forceinline__ void store_dummies(__amdgpu_buffer_rsrc_t ro, uint32_
         uint32_t o = oob;
         asm volatile("" : "+v"(o));           // separate stores, not merged into wider ones
         if constexpr (V == 4)
-            __builtin_amdgcn_raw_buffer_store_b128(uint4_t{0, 0, 0, 0}, ro, (int)o, 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b128(uint4_t{0, 0, 0, 0}, ro, (int)o, 0, kStoreNT);
         else
-            __builtin_amdgcn_raw_buffer_store_b32(0u, ro, (int)o, 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b32(0u, ro, (int)o, 0, kStoreNT);
     }
 }
 

@@ -77,13 +77,25 @@ struct PredecodeArgs {
     uint2 *texels;
 };
 
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+
+// Two texels to the scratch as one 16-byte non-temporal store: the unpack
+// never reads them back, and the decode that follows it runs faster when the
+// unpack's writes have not been left dirty in the caches (measured on the
+// frame benchmark's unpack-then-decode step).
+__device__ __forceinline__ void store_pair(uint2 *dst, uint2 t0, uint2 t1)
+{
+    __builtin_nontemporal_store((u32x4_t){t0.x, t0.y, t1.x, t1.y}, reinterpret_cast<u32x4_t *>(dst));
+}
+
 template <bool SIGNED>
 __global__ void __launch_bounds__(256) k_predecode(PredecodeArgs a)
 {
     __shared__ uint32_t table[kTableWords];
     // each lane's block palette, entry-major so that lane L's entries sit in
-    // consecutive 8-byte slots across lanes
+    // consecutive 8-byte slots across lanes, and its 16 four-bit slots
     __shared__ uint2 palette[16][256];
+    __shared__ uint2 slots[256];
     load_table(table);
     // segment of this workgroup (uniform scan over at most 64 entries)
     const uint32_t wg = blockIdx.x;
@@ -92,44 +104,73 @@ __global__ void __launch_bounds__(256) k_predecode(PredecodeArgs a)
     const TexDesc &T = a.m.tex[a.p.seg_tex[seg]];
     const uint32_t l = a.p.seg_lvl[seg];
     const uint32_t lw = max(T.w >> l, 1u), lh = max(T.h >> l, 1u);
-    const uint32_t bx = (lw + 3) / 4, by = (lh + 3) / 4;
-    const uint32_t bi = (wg - a.p.seg_wg[seg]) * 256 + threadIdx.x;
-    if (bi >= bx * by) return;
-    const uint4 b = T.blocks[T.blk_off[l] + bi];
-    Bc6hHeader h;
-    bc6h_header<SIGNED>(b.x, b.y, b.z, b.w, table, h);
-    {
+    const uint32_t bx = (lw + 3) / 4, by = (lh + 3) / 4, n_blk = bx * by;
+    const uint32_t first = (wg - a.p.seg_wg[seg]) * 256;   // this workgroup's first block
+    const uint32_t bi = first + threadIdx.x;
+    if (bi < n_blk) {
+        const uint4 b = T.blocks[T.blk_off[l] + bi];
+        Bc6hHeader h;
+        bc6h_header<SIGNED>(b.x, b.y, b.z, b.w, table, h);
         uint32_t pal[16][2];
         bc6h_palette<SIGNED>(h, pal);
 #pragma unroll
         for (int j = 0; j < 16; ++j) palette[j][threadIdx.x] = make_uint2(pal[j][0], pal[j][1]);
+        uint32_t s0 = 0, s1 = 0;
+#pragma unroll
+        for (uint32_t t = 0; t < 8; ++t) {
+            s0 |= bc6h_slot(h, t) << (4 * t);
+            s1 |= bc6h_slot(h, t + 8) << (4 * t);
+        }
+        slots[threadIdx.x] = make_uint2(s0, s1);
     }
-    const uint32_t x0 = 4 * (bi % bx), y0 = 4 * (bi / bx);
+    __syncthreads();
     const uint32_t pitch = row_pitch(lw);
     uint2 *dst = a.texels + T.tex_off[l];
-    // A level narrower or shorter than 4 texels keeps only the top-left part
-    // of its blocks in that direction.
+    auto texel = [&](uint32_t lb, uint32_t t) {     // texel t (row-major) of the block in lane lb
+        const uint2 sl = slots[lb];
+        const uint32_t j = ((t < 8 ? sl.x : sl.y) >> (4 * (t & 7))) & 15u;
+        return palette[j][lb];
+    };
+    if (lw >= 4) {
+        // A wave's 64 blocks, 32 at a time: lanes 2k and 2k + 1 write the
+        // two halves of one block row, so each store instruction covers
+        // whole 32-byte block rows (consecutive blocks of a block row are
+        // contiguous). The level starts on a multiple of 4 texels and
+        // pitch = w + 2 is even, so every store is 16-byte aligned.
+        const uint32_t lane = threadIdx.x & 63, half = lane & 1;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        if (y0 + r >= lh) break;
-        uint2 px[4];
+        for (uint32_t g = 0; g < 2; ++g) {
+            const uint32_t lb = (threadIdx.x & ~63u) + 32 * g + (lane >> 1);
+            const uint32_t bj = first + lb;
+            if (bj >= n_blk) continue;
+            const uint32_t x0 = 4 * (bj % bx), y0 = 4 * (bj / bx);
 #pragma unroll
-        for (int c = 0; c < 4; ++c) px[c] = palette[bc6h_slot(h, 4 * r + c)][threadIdx.x];
-        uint2 *row = dst + (size_t)(y0 + r) * pitch;
-        if (lw >= 4) {
-            // the level starts on a multiple of 4 texels and pitch = w + 2 is
-            // even, so these are 16-byte aligned
-            reinterpret_cast<uint4 *>(row + x0)[0] = make_uint4(px[0].x, px[0].y, px[1].x, px[1].y);
-            reinterpret_cast<uint4 *>(row + x0)[1] = make_uint4(px[2].x, px[2].y, px[3].x, px[3].y);
-            if (x0 == 0)            // wrap columns w and w+1: texels 0 and 1
-                reinterpret_cast<uint4 *>(row + lw)[0] = make_uint4(px[0].x, px[0].y, px[1].x, px[1].y);
-        } else if (lw == 2) {       // pitch 4: texels 0 1 0 1
-            reinterpret_cast<uint4 *>(row)[0] = make_uint4(px[0].x, px[0].y, px[1].x, px[1].y);
-            reinterpret_cast<uint4 *>(row)[1] = make_uint4(px[0].x, px[0].y, px[1].x, px[1].y);
-        } else {                    // pitch 3: texel 0 three times
-            row[0] = px[0];
-            row[1] = px[0];
-            row[2] = px[0];
+            for (uint32_t r = 0; r < 4; ++r) {
+                if (y0 + r >= lh) break;          // a level shorter than 4 texels
+                const uint2 p0 = texel(lb, 4 * r + 2 * half), p1 = texel(lb, 4 * r + 2 * half + 1);
+                uint2 *row = dst + (size_t)(y0 + r) * pitch;
+                store_pair(row + x0 + 2 * half, p0, p1);
+                if (x0 == 0 && half == 0)         // wrap columns w and w+1: texels 0 and 1
+                    store_pair(row + lw, p0, p1);
+            }
+        }
+    } else if (bi < n_blk) {
+        // a level narrower than 4 texels keeps only the left part of its
+        // blocks (and, shorter than 4, the top part)
+        const uint32_t y0 = 4 * (bi / bx);
+#pragma unroll
+        for (uint32_t r = 0; r < 4; ++r) {
+            if (y0 + r >= lh) break;
+            uint2 *row = dst + (size_t)(y0 + r) * pitch;
+            const uint2 p0 = texel(threadIdx.x, 4 * r), p1 = texel(threadIdx.x, 4 * r + 1);
+            if (lw == 2) {                        // pitch 4: texels 0 1 0 1
+                store_pair(row, p0, p1);
+                store_pair(row + 2, p0, p1);
+            } else {                              // pitch 3: texel 0 three times
+                row[0] = p0;
+                row[1] = p0;
+                row[2] = p0;
+            }
         }
     }
 }

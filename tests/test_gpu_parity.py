@@ -148,23 +148,25 @@ def test_fewer_textures_non_square_bias_small_levels(bcf, precision, atol):
     check(bcf, texs, sizes, lv, dims, params, bias, host, q, bcf.Precision[precision], atol)
 
 
-def test_texel_centres_reproduce_texels_on_gpu(bcf):
+@pytest.mark.parametrize("rw,rh,L", [(32, 32, 6), (256, 64, 9)])
+def test_texel_centres_reproduce_texels_on_gpu(bcf, rw, rh, L):
     # FP32 path with an identity MLP 3 -> 3 -> 3 (identity weights, zero
     # biases; the ReLU passes the non-negative UF16 features): outputs are the
-    # filtered features, and at texel centres of integer levels the texels
-    res, L = 32, 6
+    # filtered features, and at texel centres of integer levels the texels.
+    # 256 x 64: levels of several unpack workgroups, block rows of 64 blocks,
+    # and levels 2, 1 and 1 texel high under wider ones.
     g = synth.rng(9)
-    tex = synth.bounded_blocks(synth.chain_blocks(res, res, L), g).reshape(-1)
+    tex = synth.bounded_blocks(synth.chain_blocks(rw, rh, L), g).reshape(-1)
     eye = np.concatenate([np.eye(3).ravel(), np.zeros(3)])
     params = np.concatenate([eye, eye]).astype(np.float32)
-    host = oracle.Material([tex], [res], [L], (3, 3, 3), params)
+    host = oracle.Material([tex], [(rw, rh)], [L], (3, 3, 3), params)
     qs = []
     for l in range(L):
-        w = max(res >> l, 1)
-        jj, ii = np.meshgrid(np.arange(w), np.arange(w), indexing="ij")
-        qs.append(np.stack([(ii + 0.5) / w, (jj + 0.5) / w, np.full(ii.shape, l)], -1).reshape(-1, 3))
+        w, h = max(rw >> l, 1), max(rh >> l, 1)
+        jj, ii = np.meshgrid(np.arange(h), np.arange(w), indexing="ij")
+        qs.append(np.stack([(ii + 0.5) / w, (jj + 0.5) / h, np.full(ii.shape, l)], -1).reshape(-1, 3))
     q = np.concatenate(qs).astype(np.float32)
-    got = run_gpu(bcf, [tex], [(res, res)], [L], (3, 3, 3), params, [0.0], q, bcf.Precision.FP32)
+    got = run_gpu(bcf, [tex], [(rw, rh)], [L], (3, 3, 3), params, [0.0], q, bcf.Precision.FP32)
     assert np.array_equal(got, oracle.sample(host, q))
 
 
