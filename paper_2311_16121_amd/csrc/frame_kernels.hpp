@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 
 #include "filter_device.hpp"
 #include "internal.hpp"
@@ -576,21 +577,25 @@ hipError_t launch_batch_kind(const BatchArgs &a, const MlpShape &sh, unsigned gr
     return hipErrorInvalidValue;
 }
 
-// Workgroups of `kernel` resident at once on the current device (cached per
-// kernel and device).
-template <typename F>
-unsigned resident_workgroups(F kernel)
+// Workgroups of KERNEL resident at once on the current device, 0 if the
+// runtime cannot say (cached per kernel and device; concurrent first calls
+// compute the same value).
+template <auto KERNEL>
+unsigned resident_workgroups()
 {
-    static int cache[16];
+    static std::atomic<int> cache[16];
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0) return 0;
-    if (dev < 16 && cache[dev] > 0) return (unsigned)cache[dev];
+    if (dev < 16) {
+        const int c = cache[dev].load(std::memory_order_relaxed);
+        if (c > 0) return (unsigned)c;
+    }
     int per_cu = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kFrameThreads, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, KERNEL, kFrameThreads, 0) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 0;
     const int r = std::max(per_cu, 1) * std::max(cus, 1);
-    if (dev < 16) cache[dev] = r;
+    if (dev < 16) cache[dev].store(r, std::memory_order_relaxed);
     return (unsigned)r;
 }
 
@@ -613,9 +618,9 @@ hipError_t launch_frame_kind(const FrameArgs &a, const MlpShape &sh, hipStream_t
     constexpr unsigned kOversub = K == MLP_VALU_F32 ? 4 : 2;
 #define BCF_CASE(H, NH)                                                                       \
     if (sh.hidden == H && sh.n_hidden == NH) {                                               \
-        const auto kern = k_frame<K, H, NH, C, SH>;                                           \
-        const unsigned res = resident_workgroups(kern);                                      \
-        kern<<<frame_launch_grid(a.n_items, res ? kOversub * res : 4096u), kFrameThreads, 0, s>>>(a); \
+        const unsigned res = resident_workgroups<k_frame<K, H, NH, C, SH>>();                \
+        k_frame<K, H, NH, C, SH>                                                              \
+            <<<frame_launch_grid(a.n_items, res ? kOversub * res : 4096u), kFrameThreads, 0, s>>>(a); \
         return hipGetLastError();                                                             \
     }
     BCF_CASE(16, 1) BCF_CASE(16, 2) BCF_CASE(16, 3)
