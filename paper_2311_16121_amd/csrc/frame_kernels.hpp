@@ -51,9 +51,9 @@ struct FrameArgs {
     // wide: every output row this launch writes starts on a 16-byte boundary
     // and n * out_dim is a multiple of 4, so items store 16-byte chunks
     uint32_t grid_w, tiles_x, n_items, wide;
-    // tiled work: tiles_y rows of tiles; bands = kXcds splits the tile
-    // columns into one band per XCD, 1 keeps a single band
-    uint32_t tiles_y, bands;
+    // tiled work: tiles_y rows of tiles; strip_rows > 0: the tile rows form
+    // strips of that many, dealt to the XCDs in turn (0: items round-robin)
+    uint32_t tiles_y, strip_rows;
 };
 
 // Work-item tiles for queries declared as an image: 16 x 4.
@@ -61,30 +61,34 @@ constexpr uint32_t kTileLog2 = 4, kTileW = 1u << kTileLog2, kTileH = 64u >> kTil
 
 // The grid is a multiple of the 8 XCDs, to which workgroups are dispatched
 // round-robin (workgroup b runs on XCD b % 8), and a small multiple of what
-// is resident at once, so the waves sweep the image nearly together. Tiled work gives
-// each XCD a band of tile columns, walked in row order by that XCD's waves
-// in turn: the tiles in flight on an XCD at any moment are a few rows of its
-// band, whose vertical and horizontal neighbours -- sharing texels -- sit in
-// the same XCD's L2. Linear work (and images too narrow for bands) goes
+// is resident at once, so the waves sweep the image nearly together. Tiled
+// work deals strips of whole tile rows to the XCDs in turn (strip j to XCD
+// j % 8); an XCD's waves walk its strips tile by tile. Texels are shared
+// along a strip -- a textured plane that wraps repeats the same texels
+// across the image's width -- so whole-width strips keep that sharing inside
+// one XCD's L2, while the strips of different XCDs share only their edge
+// rows. Linear work (and images of fewer tile rows than XCDs) goes
 // round-robin over all waves.
 constexpr uint32_t kXcds = 8;
 
-// A wave's share of the work: items first, first + step, ... below end of a
-// band of bw tile columns starting at column c0 (linear work: bw = 1, and
-// the item's row of "tiles" is the item).
+// A wave's share of the work: items first, first + step, ... below end. In
+// strip mode item k is tile k % per of strip (k / per) * kXcds + xcd, per =
+// strip_rows * tiles_x tiles; otherwise item k is tile k (row-major).
 struct WaveWork {
-    uint32_t first, end, step, c0, bw;
+    uint32_t first, end, step, xcd, per;
 };
 
 __device__ __forceinline__ WaveWork wave_work(const FrameArgs &a, uint32_t wv)
 {
-    if (a.bands == kXcds) {
+    if (a.strip_rows) {
         const uint32_t x = blockIdx.x % kXcds;
-        const uint32_t c0 = x * a.tiles_x / kXcds, c1 = (x + 1) * a.tiles_x / kXcds;
-        return WaveWork{(blockIdx.x / kXcds) * kFrameWaves + wv, (c1 - c0) * a.tiles_y,
-                        (gridDim.x / kXcds) * kFrameWaves, c0, c1 - c0};
+        const uint32_t n_strips = (a.tiles_y + a.strip_rows - 1) / a.strip_rows;
+        const uint32_t mine = n_strips > x ? (n_strips - x + kXcds - 1) / kXcds : 0;   // strips x, x + 8, ...
+        const uint32_t per = a.strip_rows * a.tiles_x;
+        return WaveWork{(blockIdx.x / kXcds) * kFrameWaves + wv, mine * per, (gridDim.x / kXcds) * kFrameWaves, x,
+                        per};
     }
-    return WaveWork{blockIdx.x * kFrameWaves + wv, a.n_items, gridDim.x * kFrameWaves, 0, a.grid_w ? a.tiles_x : 1u};
+    return WaveWork{blockIdx.x * kFrameWaves + wv, a.n_items, gridDim.x * kFrameWaves, 0, 0};
 }
 
 struct ItemRange {
@@ -352,19 +356,28 @@ __global__ void __launch_bounds__(kFrameThreads) k_frame(FrameArgs a)
     const uint32_t oob = a.n * a.out_dim * 4u;
     const WaveWork w = wave_work(a, wv);
     if (w.first >= w.end) return;
-    // Item k of this wave's band: tile row t0 = k / bw, column c0 + k % bw.
-    // Sets `it` (the linear item, = t0) and the tile's origin, and returns this
-    // lane's query; lanes outside the image or past n read zeros (buffer
-    // range check) and their rows are not stored.
+    // Item k of this wave's share: sets `it` (the linear item, or the tile
+    // row) and the tile's origin, and returns this lane's query; lanes outside
+    // the image or past n (also whole tiles of a strip below the image) read
+    // zeros (buffer range check) and their rows are not stored.
     auto query_of = [&](uint32_t k, uint32_t &it, uint32_t &row0, uint32_t &col0) -> uint32_t {
-        const uint32_t t0 = k / w.bw;
-        it = t0;
         if (!a.grid_w) {
+            it = k;
             row0 = col0 = 0;
-            return t0 * 64 + lane;
+            return k * 64 + lane;
         }
-        row0 = t0 * kTileH;
-        col0 = (w.c0 + (k - t0 * w.bw)) * kTileW;
+        uint32_t tr, tc;
+        if (w.per) {
+            const uint32_t j = k / w.per, rem = k - j * w.per;
+            tr = (j * kXcds + w.xcd) * a.strip_rows + rem / a.tiles_x;
+            tc = rem % a.tiles_x;
+        } else {
+            tr = k / a.tiles_x;
+            tc = k - tr * a.tiles_x;
+        }
+        it = tr;
+        row0 = tr * kTileH;
+        col0 = tc * kTileW;
         const uint32_t col = col0 + (lane & (kTileW - 1u));
         const uint32_t q = (row0 + (lane >> kTileLog2)) * a.grid_w + col;
         return col < a.grid_w && q < a.n ? q : a.n;

@@ -399,6 +399,9 @@ static unsigned frame_grid(uint32_t items)
     return std::max(kXcds, (blocks + kXcds - 1) / kXcds * kXcds);
 }
 
+// tile rows per strip of a tiled frame (16 x 4 tiles: 16 image rows)
+constexpr uint32_t kStripRows = 4;
+
 hipError_t launch_filter_mlp(const MaterialDesc &m, const MlpShape &sh, MlpKind kind,
                              const WsLayout &lay, const void *ws, const float *queries, size_t n,
                              uint32_t grid_width, float *out, hipStream_t s)
@@ -426,7 +429,11 @@ hipError_t launch_filter_mlp(const MaterialDesc &m, const MlpShape &sh, MlpKind 
         a.tiles_x = (grid_width + kTileW - 1) / kTileW;
         a.tiles_y = (rows + kTileH - 1) / kTileH;
         a.n_items = a.tiles_x * a.tiles_y;
-        a.bands = a.tiles_x >= 2 * kXcds ? kXcds : 1;        // at least two tile columns per band
+        // strips of kStripRows tile rows, fewer when the image has too few
+        // tile rows to give every XCD a strip
+        a.strip_rows = 0;
+        for (uint32_t r = kStripRows; r >= 1 && !a.strip_rows; r /= 2)
+            if (a.tiles_y >= r * kXcds) a.strip_rows = r;
         a.wide = (grid_width * sh.out) % 4 == 0 && (a.n * sh.out) % 4 == 0 && ((uintptr_t)out & 15) == 0;
         return launch();
     }

@@ -294,8 +294,9 @@ def test_grid_width_does_not_change_results(bcf, dims):
     texs, sizes, lv, params, bias, host = make(64, 7, dims, "B", seed=31)
     mat = bcf.Material.from_host(texs, sizes, lv, dims, params, bias)
     g = synth.rng(32)
-    # (widths of 256 and 270 columns: 16 and 17 tile columns, the narrowest
-    # images split into one band of tile columns per XCD, evenly and not)
+    # (53, 64 and 37 columns: 10, 16 and 34 tile rows, strips of 1, 2 and 4
+    # tile rows per XCD; 256, 270 and 999 columns: fewer tile rows than XCDs,
+    # items round-robin)
     for n, width in ((53 * 37 + 17, 53), (4096, 64), (3000, 8), (999, 999), (5000, 37), (70, 9),
                      (256 * 20, 256), (270 * 9 + 5, 270)):
         q = synth.uniform_queries(n, g, 6.0)
