@@ -115,15 +115,17 @@ def sources_digest():
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_frame_fp16_frame4k_traffic.md")
+BATCH_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_batch_batch64_traffic.md")
 
 
-def measured_traffic():
-    """HBM bytes per k_frame (FP16) launch from the committed counter summary,
-    or None when it is missing or was taken from other kernel sources."""
-    if not os.path.exists(TRAFFIC_FILE):
+def measured_traffic(path=TRAFFIC_FILE):
+    """HBM bytes per launch of the kernel a committed counter summary covers
+    (k_frame FP16 on frame4k by default), or None when it is missing or was
+    taken from other kernel sources."""
+    if not os.path.exists(path):
         return None
     fields = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if line.startswith("- ") and ":" in line:
             k, v = line[2:].split(":", 1)
             fields[k.strip()] = v.strip().strip("`")
@@ -245,7 +247,8 @@ def bench_batch(args):
                    "queries": n, "materials": spec.n_materials, "texture_bytes": blocks * 16,
                    "plan": {"workgroups": plan[0], "interleave": plan[1], "tuned_decode_ms": tuned_ms}},
         "roofline": {"bound": "hbm", "kernel": "k_batch (fp16)", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(BATCH_TRAFFIC_FILE),
                      "alg_bytes_per_launch": frame_bytes, "launch_ms": decode_ms},
         "kernels": {"unpack_all": {"launch_ms": unpack_ms, "alg_bytes": unpack_bytes,
                                    "achieved": unpack_bytes / (unpack_ms * 1e-3) / 1e9}},
