@@ -193,7 +193,11 @@ bcf_status bcf_batch_workspace_size(const bcf_material *mats, uint32_t n_mats, b
 bcf_status bcf_prepare_batch(const bcf_material *mats, uint32_t n_mats, bcf_precision p, void *ws,
                              size_t ws_bytes, void *stream);
 
-/* bcf_unpack for every material of the batch (one launch per material). */
+/* bcf_unpack for every material of the batch (one launch per material).
+ * A material whose four pyramids share size, level count and bias keeps its
+ * texels position-interleaved in the batch workspace (the four pyramids'
+ * texels of one position together), so a decode reads one footprint row of
+ * all four from one span; results do not depend on the layout. */
 bcf_status bcf_unpack_batch(const bcf_material *mats, uint32_t n_mats, void *ws, void *stream);
 
 /* Decodes every material's queries in one persistent launch (after a small

@@ -143,11 +143,36 @@ bcf_status describe(const bcf_material *m, bcf::MaterialDesc *d, bcf::MlpShape *
     return BCF_OK;
 }
 
+// 8-byte units of a material's texel scratch
 size_t scratch_texels(const bcf::MaterialDesc &d)
 {
     const bcf::TexDesc &T = d.tex[d.n_tex - 1];
     const uint32_t l = T.levels - 1;
-    return align_up(T.tex_off[l] + (size_t)scratch_pitch(level_dim(T.w, l)) * level_dim(T.h, l), 4);
+    const size_t end = align_up(T.tex_off[l] + (size_t)scratch_pitch(level_dim(T.w, l)) * level_dim(T.h, l), 4);
+    return d.interleaved ? end * bcf::kMaxTextures : end;
+}
+
+// Switch a material whose four pyramids share one geometry to the
+// position-interleaved scratch (MaterialDesc::interleaved); others keep the
+// per-pyramid layout.
+void interleave_if_shared(bcf::MaterialDesc &d)
+{
+    if (d.n_tex != (uint32_t)bcf::kMaxTextures) return;
+    const bcf::TexDesc &A = d.tex[0];
+    for (uint32_t t = 1; t < d.n_tex; ++t) {
+        const bcf::TexDesc &B = d.tex[t];
+        if (A.w != B.w || A.h != B.h || A.levels != B.levels || A.bias != B.bias) return;
+    }
+    size_t pos = 0;
+    uint32_t off[bcf::kMaxLevels];
+    for (uint32_t l = 0; l < A.levels; ++l) {
+        off[l] = (uint32_t)pos;
+        pos = align_up(pos + (size_t)scratch_pitch(level_dim(A.w, l)) * level_dim(A.h, l), 4);
+    }
+    if (pos * bcf::kMaxTextures > kMaxScratchTexels) return;
+    for (uint32_t t = 0; t < d.n_tex; ++t)
+        for (uint32_t l = 0; l < A.levels; ++l) d.tex[t].tex_off[l] = off[l];
+    d.interleaved = 1;
 }
 
 size_t elem_bytes(bcf::MlpKind k)
@@ -194,9 +219,10 @@ bcf::PredecodePlan predecode_plan(const bcf::MaterialDesc &d)
     bcf::PredecodePlan p;
     std::memset(&p, 0, sizeof p);
     uint32_t wg = 0;
-    for (uint32_t t = 0; t < d.n_tex; ++t)
+    for (uint32_t t = 0; t < (d.interleaved ? 1u : d.n_tex); ++t)
         for (uint32_t l = 0; l < d.tex[t].levels; ++l) {
-            const uint32_t nb = (uint32_t)(((level_dim(d.tex[t].w, l) + 3) / 4) * ((level_dim(d.tex[t].h, l) + 3) / 4));
+            uint32_t nb = (uint32_t)(((level_dim(d.tex[t].w, l) + 3) / 4) * ((level_dim(d.tex[t].h, l) + 3) / 4));
+            if (d.interleaved) nb *= bcf::kMaxTextures;        // one lane per (block, pyramid)
             p.seg_tex[p.n_seg] = t;
             p.seg_lvl[p.n_seg] = l;
             p.seg_wg[p.n_seg] = wg;
@@ -365,6 +391,7 @@ bcf_status describe_batch(const bcf_material *mats, uint32_t n_mats, bcf_precisi
                    std::memcmp(sh.dims, b->sh.dims, sizeof(uint32_t) * (sh.n_layers + 1)) != 0) {
             return fail(BCF_ERR_INVALID_ARG, "material %u: MLP dims differ from material 0", k);
         }
+        interleave_if_shared(b->descs[k]);
         b->slots[k].scratch_off = off;
         b->slots[k].scratch_bytes = scratch_texels(b->descs[k]) * 8;
         off = align_up(off + b->slots[k].scratch_bytes, 256);

@@ -248,6 +248,22 @@ __device__ __forceinline__ void decode_wave(const Query &qq, __amdgpu_buffer_rsr
     mlp_stage<K, H, NH, C>(z, wbase, lay, mlp, feats, st, out_dim, lane);
 }
 
+// decode_wave for a material with a position-interleaved scratch
+template <MlpKind K, int H, int NH, int C>
+__device__ __forceinline__ void decode_wave_interleaved(const Query &qq, __amdgpu_buffer_rsrc_t rs,
+                                                        const LevelLut &lut, const float *levels_bias,
+                                                        const uint8_t *wbase, const WsLayout &lay,
+                                                        const MfmaMlp<K == MLP_VALU_F32 ? MLP_MFMA_F16 : K, H, NH> &mlp,
+                                                        float4_t (*feats)[4], float *st, uint32_t out_dim,
+                                                        uint32_t lane)
+{
+    PendingTaps taps;
+    fetch4_interleaved(rs, lut, levels_bias, qq.u, qq.v, qq.s, taps);
+    float z[12];
+    filter_pending(taps, z);
+    mlp_stage<K, H, NH, C>(z, wbase, lay, mlp, feats, st, out_dim, lane);
+}
+
 // Item `it` of a run of n consecutive queries: its (up to) 64 staged rows go
 // to out as 16-byte stores, the last partial item as 4-byte stores.
 __device__ __forceinline__ void store_run(const float4_t *stage, __amdgpu_buffer_rsrc_t ro, uint32_t it, uint32_t n,
@@ -476,7 +492,7 @@ struct BatchMat {
     LevelLut lut;                          // as FrameArgs, offsets within the material's scratch
     float levels_bias[2 * kMaxTextures];
     uint64_t scratch_off, weights_off;     // bytes from the workspace start
-    uint32_t scratch_bytes, stride, shared, pad;
+    uint32_t scratch_bytes, stride, shared, interleaved;   // interleaved: as MaterialDesc
 };
 
 struct BatchArgs {
@@ -527,7 +543,7 @@ __global__ void __launch_bounds__(kFrameThreads) k_batch(BatchArgs a)
     }
 
     MfmaMlp<VALU ? MLP_MFMA_F16 : K, H, NH> mlp;
-    uint32_t cur = 0xFFFFFFFFu, first_item = 0, n_k = 0, shared = 0, stride = 0;
+    uint32_t cur = 0xFFFFFFFFu, first_item = 0, n_k = 0, shared = 0, interleaved = 0, stride = 0;
     float lb[2 * kMaxTextures];
     const uint8_t *wbase = a.ws;
     __amdgpu_buffer_rsrc_t rs = make_rsrc(a.ws, 0), rq = rs, ro = rs;
@@ -549,6 +565,7 @@ __global__ void __launch_bounds__(kFrameThreads) k_batch(BatchArgs a)
             for (int j = 0; j < 2 * kMaxTextures; ++j)
                 lb[j] = __builtin_bit_cast(float, uniform(__builtin_bit_cast(uint32_t, M.levels_bias[j])));
             shared = uniform(M.shared);
+            interleaved = uniform(M.interleaved);
             stride = uniform(M.stride);
             rs = make_rsrc(a.ws + uniform64(M.scratch_off), uniform(M.scratch_bytes));
             uint32_t q0;
@@ -564,7 +581,10 @@ __global__ void __launch_bounds__(kFrameThreads) k_batch(BatchArgs a)
         }
         const uint32_t j = it - first_item;
         const Query qq = load_query(rq, j * 64 + lane);   // past n_k: zeros, not stored
-        if (shared)
+        if (interleaved)
+            decode_wave_interleaved<K, H, NH, C>(qq, rs, lut[wv], lb, wbase, a.lay, mlp, feats, st, a.out_dim,
+                                                 lane);
+        else if (shared)
             decode_wave<K, H, NH, C, true>(qq, rs, lut[wv], lb, stride, wbase, a.lay, mlp, feats, st,
                                            a.out_dim, lane);
         else

@@ -28,6 +28,12 @@ struct MaterialDesc {
     TexDesc tex[kMaxTextures];
     uint32_t n_tex;
     uint32_t is_signed;
+    // 1: the four pyramids share one geometry and their texel scratch is
+    // position-interleaved -- texel (x, y) of level l of all four pyramids in
+    // one 32-byte position (pyramid t at byte 8t), tex_off counting positions
+    // and equal for every pyramid -- so a footprint row of all four pyramids
+    // is one 64-byte span. 0: each pyramid's levels back to back (8-byte texels).
+    uint32_t interleaved;
 };
 
 // MLP arithmetic variants
@@ -58,6 +64,8 @@ struct WsLayout {
 hipError_t launch_decode_blocks(const uint4 *blocks, size_t n, uint32_t is_signed, uint16_t *out,
                                 hipStream_t s);
 
+// Unpack segments: one per (pyramid, level), or one per level of an
+// interleaved scratch (four lanes per block position, one per pyramid).
 struct PredecodePlan {
     uint32_t n_seg;
     uint32_t seg_tex[kMaxTextures * kMaxLevels];

@@ -101,12 +101,16 @@ __global__ void __launch_bounds__(256) k_predecode(PredecodeArgs a)
     const uint32_t wg = blockIdx.x;
     uint32_t seg = 0;
     while (seg + 1 < a.p.n_seg && a.p.seg_wg[seg + 1] <= wg) ++seg;
-    const TexDesc &T = a.m.tex[a.p.seg_tex[seg]];
     const uint32_t l = a.p.seg_lvl[seg];
+    // interleaved scratch: lane = 4 * block + pyramid, all four pyramids of a
+    // level in one segment; otherwise lane = block of the segment's pyramid
+    const uint32_t il = a.m.interleaved;
+    const uint32_t li = (wg - a.p.seg_wg[seg]) * 256 + threadIdx.x;
+    const TexDesc &T = a.m.tex[il ? (li & 3u) : a.p.seg_tex[seg]];
     const uint32_t lw = max(T.w >> l, 1u), lh = max(T.h >> l, 1u);
     const uint32_t bx = (lw + 3) / 4, by = (lh + 3) / 4, n_blk = bx * by;
-    const uint32_t first = (wg - a.p.seg_wg[seg]) * 256;   // this workgroup's first block
-    const uint32_t bi = first + threadIdx.x;
+    const uint32_t first = (wg - a.p.seg_wg[seg]) * 256;   // this workgroup's first block (per-pyramid layout)
+    const uint32_t bi = il ? li >> 2 : li;
     if (bi < n_blk) {
         const uint4 b = T.blocks[T.blk_off[l] + bi];
         Bc6hHeader h;
@@ -125,12 +129,43 @@ __global__ void __launch_bounds__(256) k_predecode(PredecodeArgs a)
     }
     __syncthreads();
     const uint32_t pitch = row_pitch(lw);
-    uint2 *dst = a.texels + T.tex_off[l];
     auto texel = [&](uint32_t lb, uint32_t t) {     // texel t (row-major) of the block in lane lb
         const uint2 sl = slots[lb];
         const uint32_t j = ((t < 8 ? sl.x : sl.y) >> (4 * (t & 7))) & 15u;
         return palette[j][lb];
     };
+    if (il) {
+        // A wave holds 16 blocks (four lanes each, one per pyramid). Each
+        // block row is one 128-byte line of four 32-byte positions; a store
+        // instruction writes eight whole lines: lane L takes 16 bytes
+        // (position L % 8 / 2 of the row, pyramids 2(L%2) and 2(L%2)+1) of
+        // block 8h + L / 8, read through LDS from that block's lanes.
+        // Non-temporal like the per-pyramid layout's stores.
+        const uint32_t lane = threadIdx.x & 63u, wave0 = threadIdx.x & ~63u;
+        const uint32_t chunk = lane & 7u, pp = 2 * (lane & 1u), cpos = chunk >> 1;
+        for (uint32_t h = 0; h < 2; ++h) {
+            const uint32_t blw = 8 * h + (lane >> 3);                     // block within the wave
+            const uint32_t bj = ((li - lane) >> 2) + blw;                 // its index in the level
+            if (bj >= n_blk) continue;
+            const uint32_t lb = wave0 + 4 * blw + pp;                     // LDS lane of pyramid pp
+            const uint32_t x0 = 4 * (bj % bx), y0 = 4 * (bj / bx);
+            uint2 *dst = a.texels + (size_t)kMaxTextures * T.tex_off[l] + pp;
+            for (uint32_t r = 0; r < 4; ++r) {
+                if (y0 + r >= lh) break;
+                uint2 *row = dst + (size_t)kMaxTextures * (y0 + r) * pitch;
+                // lw >= 4: texel column cpos; lw = 2: columns 0 1 0 1 (pitch 4);
+                // lw = 1: texel 0 at positions 0 1 2 (pitch 3)
+                if (lw == 1 && cpos >= 3) continue;
+                const uint32_t col = lw >= 4 ? cpos : lw == 2 ? (cpos & 1u) : 0u;
+                const uint2 p0 = texel(lb, 4 * r + col), p1 = texel(lb + 1, 4 * r + col);
+                store_pair(row + kMaxTextures * (x0 + cpos), p0, p1);
+                if (lw >= 4 && x0 == 0 && cpos < 2)                        // wrap positions w, w + 1
+                    store_pair(row + kMaxTextures * (lw + cpos), p0, p1);
+            }
+        }
+        return;
+    }
+    uint2 *dst = a.texels + T.tex_off[l];
     if (lw >= 4) {
         // A wave's 64 blocks, 32 at a time: lanes 2k and 2k + 1 write the
         // two halves of one block row, so each store instruction covers
@@ -489,6 +524,7 @@ hipError_t write_batch_table(const MaterialDesc *mats, const BatchSlot *slots, u
         b.scratch_bytes = (uint32_t)slots[k].scratch_bytes;
         b.stride = a.stride;
         b.shared = shared ? 1u : 0u;
+        b.interleaved = mats[k].interleaved;
     }
     hipError_t e = hipMemcpyAsync(static_cast<uint8_t *>(ws) + table_off, table.data(), sizeof(BatchMat) * n_mats,
                                   hipMemcpyHostToDevice, s);
