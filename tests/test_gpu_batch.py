@@ -52,16 +52,16 @@ SHAPES = [
 SHARED_SHAPES = [sh for sh in SHAPES if len(set(map(str, sh[0]))) == 1 and len(set(sh[1])) == 1]
 
 
-def make_batch(bcf, shapes=SHAPES, seed=61):
+def make_batch(bcf, shapes=SHAPES, seed=61, dims=DIMS):
     g = synth.rng(seed)
     host, mats, qs = [], [], []
     for k, (sizes, levels, n, signed) in enumerate(shapes):
         sz = [(s, s) if isinstance(s, int) else s for s in sizes]
         texs = [synth.bounded_blocks(synth.chain_blocks(w, h, L), g, signed=signed).reshape(-1)
                 for (w, h), L in zip(sz, levels)]
-        params = synth.mlp_params(DIMS, g)
-        host.append(oracle.Material(texs, sz, levels, DIMS, params, [0.0] * 4, signed))
-        mats.append(bcf.Material.from_host(texs, sz, levels, DIMS, params, signed=signed))
+        params = synth.mlp_params(dims, g)
+        host.append(oracle.Material(texs, sz, levels, dims, params, [0.0] * len(sz), signed))
+        mats.append(bcf.Material.from_host(texs, sz, levels, dims, params, signed=signed))
         qs.append(synth.uniform_queries(n, g, float(max(levels) - 1)))
     offsets = np.concatenate([[0], np.cumsum([len(q) for q in qs])]).astype(np.int32)
     return host, mats, qs, offsets
@@ -92,6 +92,27 @@ def test_batch_equals_single_material_decodes(bcf, precision, shared_only):
         err = np.abs(out[offsets[k] + pick] - ref).max()
         log(f"batch {precision} material {k}: max abs err {err:.3e}")
         assert err <= bar
+
+
+@pytest.mark.parametrize("n_pyr", [2, 3])
+def test_batch_of_fewer_pyramids_equals_single_decodes(bcf, n_pyr):
+    # materials of two or three pyramids (one geometry per material, so the
+    # shared-footprint path without the four-pyramid interleaved scratch, and
+    # one of differing sizes), 3 * n_pyr MLP inputs
+    dims = (3 * n_pyr, 32, 10)
+    shapes = [([64] * n_pyr, [7] * n_pyr, 2000, False), ([(128, 32)] * n_pyr, [8] * n_pyr, 777, False),
+              ([64, 32, 16][:n_pyr], [7, 6, 5][:n_pyr], 300, False)]
+    host, mats, qs, offsets = make_batch(bcf, shapes, seed=67, dims=dims)
+    for precision in ("FP16", "FP32"):
+        prec = bcf.Precision[precision]
+        batch = bcf.Batch(mats, prec)
+        batch.unpack()
+        out = batch.decode(dev(np.concatenate(qs)), dev(offsets)).cpu().numpy()
+        for k, m in enumerate(mats):
+            ref = bcf.decode(m, bcf.prepare(m, prec), dev(qs[k]), prec).cpu().numpy()
+            assert np.array_equal(out[offsets[k]: offsets[k + 1]].view(np.uint32), ref.view(np.uint32)), (k, precision)
+        err = np.abs(out[: offsets[1]] - oracle.decode(host[0], qs[0])).max()
+        assert err <= (1e-5 if precision == "FP32" else 2e-3), (precision, err)
 
 
 def test_batch_offsets_are_clamped_and_uncovered_rows_untouched(bcf):
