@@ -52,7 +52,8 @@ struct FrameArgs {
     // and n * out_dim is a multiple of 4, so items store 16-byte chunks
     uint32_t grid_w, tiles_x, n_items, wide;
     // tiled work: tiles_y rows of tiles; strip_rows > 0: the tile rows form
-    // strips of that many, dealt to the XCDs in turn (0: items round-robin)
+    // strips of that many, dealt to the XCDs in turn (0: items round-robin).
+    // Linear work is laid out the same way, as rows of tiles_x items.
     uint32_t tiles_y, strip_rows;
 };
 
@@ -67,9 +68,11 @@ constexpr uint32_t kTileLog2 = 4, kTileW = 1u << kTileLog2, kTileH = 64u >> kTil
 // along a strip -- a textured plane that wraps repeats the same texels
 // across the image's width -- so whole-width strips keep that sharing inside
 // one XCD's L2, while the strips of different XCDs share only their edge
-// rows. Linear work (and images of fewer tile rows than XCDs) goes
-// round-robin over all waves.
+// rows. Linear work is dealt the same way in runs of kLinearRun items
+// (consecutive queries share texels along a scanline); images or runs too
+// few to give every XCD one go round-robin over all waves.
 constexpr uint32_t kXcds = 8;
+constexpr uint32_t kLinearRun = 64;     // 64-query items per run of linear work dealt to one XCD
 
 // A wave's share of the work: items first, first + step, ... below end. In
 // strip mode item k is tile k % per of strip (k / per) * kXcds + xcd, per =
@@ -377,11 +380,6 @@ __global__ void __launch_bounds__(kFrameThreads) k_frame(FrameArgs a)
     // the image or past n (also whole tiles of a strip below the image) read
     // zeros (buffer range check) and their rows are not stored.
     auto query_of = [&](uint32_t k, uint32_t &it, uint32_t &row0, uint32_t &col0) -> uint32_t {
-        if (!a.grid_w) {
-            it = k;
-            row0 = col0 = 0;
-            return k * 64 + lane;
-        }
         uint32_t tr, tc;
         if (w.per) {
             const uint32_t j = k / w.per, rem = k - j * w.per;
@@ -390,6 +388,11 @@ __global__ void __launch_bounds__(kFrameThreads) k_frame(FrameArgs a)
         } else {
             tr = k / a.tiles_x;
             tc = k - tr * a.tiles_x;
+        }
+        if (!a.grid_w) {                  // linear work: rows of tiles_x items
+            it = tr * a.tiles_x + tc;
+            row0 = col0 = 0;
+            return it * 64 + lane;
         }
         it = tr;
         row0 = tr * kTileH;

@@ -479,6 +479,9 @@ hipError_t launch_filter_mlp(const MaterialDesc &m, const MlpShape &sh, MlpKind 
         a.out = out + sh.out * first;
         a.n = cnt;
         a.n_items = (cnt + 63) / 64;
+        a.tiles_x = kLinearRun;
+        a.tiles_y = (a.n_items + kLinearRun - 1) / kLinearRun;
+        a.strip_rows = a.tiles_y >= kXcds ? 1 : 0;
         a.wide = (cnt * sh.out) % 4 == 0 && ((uintptr_t)a.out & 15) == 0;
         const hipError_t e = launch();
         if (e != hipSuccess) return e;
