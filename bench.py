@@ -414,7 +414,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(queries shard trivially across GPUs, but this build measures one).", file=sys.stderr)
+              "(queries shard across GPUs with no communication; the figure reported is one GPU's).", file=sys.stderr)
         sys.exit(2)
 
     import torch
