@@ -2,8 +2,8 @@
 bounded blocks, modes uniform over 14), MLP 12-64-64-10, 2^24 uniform
 queries, the MLP in fp32 (vector ALU), fp32 / bf16 / fp16 / fp8 on MFMA with
 fp32 accumulation. Reports per-channel max and mean absolute error against the
-fp64 oracle over every query; the report is written to
-gpurun_out/precision_sweep.json when that folder exists."""
+fp64 oracle over every query; the report is also written, as JSON, to the
+path in the environment variable BCF_PRECISION_SWEEP_JSON when it is set."""
 import json
 import os
 
@@ -52,6 +52,7 @@ def test_precision_sweep():
         if bar is not None:
             assert err.max() <= bar
         del ws, out
-    if os.path.isdir("gpurun_out"):
-        with open(os.path.join("gpurun_out", "precision_sweep.json"), "w") as f:
+    path = os.environ.get("BCF_PRECISION_SWEEP_JSON")
+    if path:
+        with open(path, "w") as f:
             json.dump(report, f, indent=1)
