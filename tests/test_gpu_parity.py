@@ -331,3 +331,41 @@ def test_output_view_writes_only_its_rows(bcf, dims):
             got = big.cpu().numpy()
             assert np.isnan(got[:lead]).all() and np.isnan(got[lead + n:]).all(), (n, width, lead, p)
             assert np.array_equal(got[lead: lead + n].view(np.uint32), ref.view(np.uint32)), (n, width, lead, p)
+
+
+def test_query_counts_beyond_one_launch(bcf):
+    # One launch takes at most 2^25 queries (32-bit byte offsets: 2^25 rows of
+    # 16 fp32 outputs are 2 GiB). 2^25 + 4097 queries with 16 outputs run as
+    # a launch of exactly that maximum and a ragged one: sampled rows on both
+    # sides of the boundary against the oracle, and the whole call bit-equal
+    # to the two halves decoded on their own and to the call with a declared
+    # image width (too many queries for tiles: the same runs)
+    dims = (12, 16, 16, 16)
+    texs, sizes, lv, params, bias, host = make(256, 9, dims, "B", seed=41)
+    mat = bcf.Material.from_host(texs, sizes, lv, dims, params, bias)
+    n0 = 1 << 25
+    n = n0 + 4097
+    q = synth.uniform_queries(n, synth.rng(42), 8.0)
+    qd = dev(q)
+    pick = np.unique(np.concatenate([synth.rng(43).choice(n, size=3000, replace=False),
+                                     np.arange(64), np.arange(n0 - 70, n0 + 70), np.arange(n - 70, n)]))
+    ref = oracle.decode(host, q[pick])
+    pick_d = torch.from_numpy(pick).cuda()
+    for p, bar in (("FP32", 1e-5), ("FP16", 2e-3)):
+        prec = bcf.Precision[p]
+        ws = bcf.prepare(mat, prec)
+        log(f"{p}: {n} queries")
+        whole = bcf.decode(mat, ws, qd, prec)
+        got = whole[pick_d].cpu().numpy().astype(np.float64)
+        err = np.abs(got - ref).max()
+        log(f"  max abs err {err:.3e} on {len(pick)} sampled queries")
+        assert np.isfinite(got).all() and err <= bar
+        head = bcf.decode(mat, ws, qd[:n0], prec)
+        assert torch.equal(whole[:n0].view(torch.int32), head.view(torch.int32))
+        del head
+        tail = bcf.decode(mat, ws, qd[n0:], prec)
+        assert torch.equal(whole[n0:].view(torch.int32), tail.view(torch.int32))
+        tiled = bcf.decode(mat, ws, qd, prec, grid_width=4096)
+        assert torch.equal(tiled.view(torch.int32), whole.view(torch.int32))
+        del ws, whole, tail, tiled
+        torch.cuda.empty_cache()
