@@ -264,7 +264,8 @@ typedef struct {
 bcf_status bcf_train_workspace_size(const bcf_train_material *m, size_t *ws_bytes);
 
 /* G(u, v, s) for n queries (device [n][3]) into out (device [n][dims[n_layers]]),
- * evaluated from the current parameters. */
+ * evaluated from the current parameters. At most 2^25 queries per call
+ * (BCF_ERR_UNSUPPORTED beyond); n == 0 is a no-op. */
 bcf_status bcf_train_forward(const bcf_train_material *m, void *ws, const float *queries, size_t n,
                              float *out, void *stream);
 
@@ -273,7 +274,8 @@ bcf_status bcf_train_forward(const bcf_train_material *m, void *ws, const float 
  * texture i's endpoint layout), grad_indices[i] and grad_params (device, the
  * params layout) with dL/d parameter. grad_endpoints and grad_indices are host
  * arrays of n_textures device pointers. Sums use float atomics, so results
- * vary in the last bits from run to run. */
+ * vary in the last bits from run to run. At most 2^25 queries per call
+ * (BCF_ERR_UNSUPPORTED beyond). */
 bcf_status bcf_train_backward(const bcf_train_material *m, void *ws, const float *queries, size_t n,
                               const float *grad_out, float *const *grad_endpoints,
                               float *const *grad_indices, float *grad_params, void *stream);
