@@ -101,7 +101,8 @@ def pack_many(mode: int, fields: dict, indices: np.ndarray) -> np.ndarray:
 
 
 def bounded_blocks(n: int, g: np.random.Generator, modes=ALL_MODES,
-                   fraction: float = 0.48, signed: bool = False) -> np.ndarray:
+                   fraction: float = 0.48, signed: bool = False,
+                   extreme_indices: bool = False) -> np.ndarray:
     """Variant B: every endpoint is drawn below cap = floor(fraction * 2^bits)
     of its mode's precision, so every decoded UF16 texel stays below 1.0 and
     absolute error targets are meaningful. Transformed modes draw each other
@@ -110,7 +111,11 @@ def bounded_blocks(n: int, g: np.random.Generator, modes=ALL_MODES,
 
     signed=True draws endpoints in (-cap, cap) with cap = floor(fraction *
     2^(bits-1)) and stores them as two's complement of the mode's precision,
-    so every decoded SF16 texel lies in (-1, 1)."""
+    so every decoded SF16 texel lies in (-1, 1).
+
+    extreme_indices=True draws every index from {0, largest}: texel 0 and the
+    subset-1 anchor (one index bit fewer) take 0, every other texel 0 or the
+    largest index, so each texel shows one endpoint unblended."""
     pick = np.asarray(modes)[g.integers(0, len(modes), size=n)]
     out = np.empty((n, 16), np.uint8)
     for m in modes:
@@ -138,11 +143,17 @@ def bounded_blocks(n: int, g: np.random.Generator, modes=ALL_MODES,
                     fields[ch + name] = g.integers(low, cap, size=k) & wrap
         width = 3 if subsets == 2 else 4
         fields["d"] = g.integers(0, 32, size=k) if subsets == 2 else np.zeros(k, np.int64)
-        idx = g.integers(0, 1 << width, size=(k, 16))
-        idx[:, 0] >>= 1                                   # texel 0 drops its top bit
-        if subsets == 2:
-            anchor = np.asarray(ANCHOR2)[fields["d"]]
-            idx[np.arange(k), anchor] >>= 1
+        if extreme_indices:
+            idx = g.integers(0, 2, size=(k, 16)) * ((1 << width) - 1)
+            idx[:, 0] = 0
+            if subsets == 2:
+                idx[np.arange(k), np.asarray(ANCHOR2)[fields["d"]]] = 0
+        else:
+            idx = g.integers(0, 1 << width, size=(k, 16))
+            idx[:, 0] >>= 1                               # texel 0 drops its top bit
+            if subsets == 2:
+                anchor = np.asarray(ANCHOR2)[fields["d"]]
+                idx[np.arange(k), anchor] >>= 1
         out[sel] = pack_many(m, fields, idx)
     return out
 

@@ -113,3 +113,39 @@ def test_signed_bounded_blocks_match_pillow(mode):
     g = synth.rng(400 + mode)
     blocks = synth.bounded_blocks(64 * 64, g, modes=(mode,))
     compare(blocks, mode in LOW_PRECISION_MODES, signed=True)
+
+
+ENDPOINT_FIELDS = {c + f for c in "rgb" for f in "wxyz"}
+
+
+@pytest.mark.parametrize("mode", range(1, 15))
+def test_every_endpoint_bit_matches_pillow_at_full_precision(mode):
+    # With every index 0 or the largest, each texel shows one endpoint
+    # unblended (weights 0 and 64), where Pillow's blend and the format's agree
+    # exactly, so any block decodes identically at 8 bits in both readers.
+    # Flipping one endpoint bit moves an endpoint by one unit of that bit; for
+    # the low-order bits of the wide fields (mode 14's rw[3:0], the deltas,
+    # the low bits of modes 12 and 13) the texel then crosses an 8-bit step
+    # only when it sat just below one, so the two readers must agree on which
+    # flips cross: a swapped or misplaced low bit changes which texels cross.
+    from synth.bc6h_pack import POSITIONS
+    g = synth.rng(500 + mode)
+    base = synth.bounded_blocks(2048, g, modes=(mode,), extreme_indices=True)
+    ref_base = oracle_8bit(base)
+    assert np.array_equal(pillow_decode(base), ref_base)
+    flipped, fields = [], []
+    for p, (name, k) in enumerate(POSITIONS[mode]):
+        if name not in ENDPOINT_FIELDS:
+            continue                        # mode code, partition: covered by the flip test above
+        b = base.copy()
+        b[:, p >> 3] ^= np.uint8(1 << (p & 7))
+        flipped.append(b)
+        fields.append((name, k))
+    flipped = np.concatenate(flipped)
+    ref = pillow_decode(flipped)
+    got = oracle_8bit(flipped)
+    assert np.array_equal(got, ref), int((got != ref).sum())
+    # the check is informative for every low-order bit: enough flips cross a step
+    crossed = (ref.reshape(len(fields), -1, 16, 3) != ref_base[None]).sum(axis=(1, 2, 3))
+    low = [(f, c) for f, c in zip(fields, crossed) if f[1] < 4]
+    assert low and all(c >= 16 for _, c in low), low
