@@ -99,16 +99,28 @@ const char *bcf_last_error(void);
  * Returns 0 for invalid sizes. */
 size_t bcf_texture_bytes(uint32_t width, uint32_t height, uint32_t levels);
 
-/* Workspace for decoding `m` at precision `p`.
+/* Workspace for decoding `m` at precision `p`: the decoder's weights in the
+ * form the kernels read (Section 5.2 ships the MLP weights as a small fp16
+ * binary beside the mip-mapped BC6 textures; this call builds that buffer,
+ * at the chosen precision, from the binary32 parameters).
  * Size query: with ws == NULL, writes the required size (bytes, 256-byte
  * aligned start required) to *ws_bytes and returns.
  * Fill: with ws != NULL (device) and *ws_bytes >= the size, converts the MLP
  * parameters into the kernels' padded layout for `p` (rounding to fp16/bf16
  * or e4m3 with per-layer scales; binary32 stays exact) asynchronously on
- * `stream`. The workspace also holds the texel scratch that bcf_unpack
- * writes and the decode reads, so one workspace serves one decode at a time;
- * the material's params must not change between prepare and decode without
- * preparing again, nor its textures without unpacking again. */
+ * `stream`, and writes a 256-byte header at ws (magic "BCFW", ABI version,
+ * precision, a hash of the material's pyramid geometry, block and parameter
+ * addresses and MLP shape, and the layout's offsets). The library also
+ * remembers that tag per workspace address on the host: bcf_decode,
+ * bcf_unpack, bcf_decode_unpacked and bcf_calibrate return
+ * BCF_ERR_INVALID_ARG for a workspace that no bcf_prepare filled, or that
+ * was prepared for another precision or another material, without reading
+ * device memory. The workspace also holds the texel scratch that bcf_unpack
+ * (and bcf_decode) WRITE and the decode reads, so one workspace serves one
+ * decode at a time: two decodes that share a workspace must be ordered on
+ * one stream. The material's parameter values must not change between
+ * prepare and decode without preparing again, nor its textures without
+ * unpacking again. */
 bcf_status bcf_prepare(const bcf_material *m, bcf_precision p, void *ws,
                        size_t *ws_bytes, void *stream);
 
@@ -122,7 +134,9 @@ bcf_status bcf_prepare(const bcf_material *m, bcf_precision p, void *ws,
  * n == 0 is a no-op. out must not overlap queries, ws or the material.
  * Non-finite query components produce unspecified values but never an
  * out-of-bounds access. Same as bcf_unpack followed by bcf_decode_unpacked
- * on `stream`; ws (prepared for `p`) receives the unpacked texels. */
+ * on `stream`: ws (prepared for `p` and this material) is written -- it
+ * receives the unpacked texels -- so concurrent decodes need one workspace
+ * each. */
 bcf_status bcf_decode(const bcf_material *m, bcf_precision p, void *ws,
                       const float *queries, size_t n, uint32_t grid_width,
                       float *out, void *stream);
@@ -172,7 +186,13 @@ bcf_status bcf_decode_blocks(const void *blocks, size_t n_blocks, uint32_t is_si
  * the kernels: a captured graph replays with whatever the caller has written
  * there since. The kernels clamp every offset to [0, n_total] (n_total = rows
  * of queries and out), treat a decreasing pair as an empty material and decode
- * at most 2^25 queries per material; rows no material covers are not written.
+ * at most 2^25 queries per material (the first 2^25 of a longer range); rows
+ * no material covers are not written. Offsets are expected non-decreasing:
+ * with a later offset below an earlier one, two materials' ranges can
+ * overlap, and each then writes the shared rows, in unspecified order. The
+ * calls that take a batch workspace return BCF_ERR_INVALID_ARG when it was
+ * not filled by bcf_prepare_batch for these materials (and, for the decode
+ * and the tuner, this precision).
  * ------------------------------------------------------------------------ */
 
 /* Launch shape of bcf_decode_batch (bcf_tune_batch picks one). */

@@ -10,7 +10,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "internal.hpp"
@@ -143,6 +145,97 @@ bcf_status describe(const bcf_material *m, bcf::MaterialDesc *d, bcf::MlpShape *
     return BCF_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Workspace tags. bcf_prepare / bcf_prepare_batch record, per workspace
+// address, the precision and a hash of what the workspace was laid out for
+// (pyramid geometry and block addresses, MLP shape and parameter address,
+// the fp8 activation ranges' address); later calls on that workspace compare
+// against the record on the host, so a mismatch is an argument error found
+// without reading device memory. The same tag is written into the
+// workspace's header.
+
+constexpr uint64_t kFnvOffset = 1469598103934665603ull, kFnvPrime = 1099511628211ull;
+
+uint64_t fnv(uint64_t h, const void *p, size_t n)
+{
+    const uint8_t *b = static_cast<const uint8_t *>(p);
+    for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * kFnvPrime;
+    return h;
+}
+
+template <typename T> uint64_t fnv_val(uint64_t h, T v) { return fnv(h, &v, sizeof v); }
+
+// a material that describe() accepted
+uint64_t material_hash(uint64_t h, const bcf_material *m, bcf_precision p)
+{
+    h = fnv_val(h, m->n_textures);
+    h = fnv_val(h, m->is_signed);
+    for (uint32_t t = 0; t < m->n_textures; ++t) {
+        const bcf_texture &x = m->textures[t];
+        h = fnv_val(h, reinterpret_cast<uintptr_t>(x.blocks));
+        h = fnv_val(h, x.width);
+        h = fnv_val(h, x.height);
+        h = fnv_val(h, x.levels);
+        h = fnv_val(h, x.lod_bias);
+    }
+    h = fnv_val(h, m->n_layers);
+    h = fnv(h, m->dims, sizeof(uint32_t) * (m->n_layers + 1));
+    h = fnv_val(h, reinterpret_cast<uintptr_t>(m->params));
+    if (p == BCF_FP8) h = fnv_val(h, reinterpret_cast<uintptr_t>(m->act_absmax));
+    return h;
+}
+
+struct WsTag {
+    int precision;
+    uint32_t n_materials;
+    uint64_t hash;
+};
+
+std::mutex g_tags_mu;
+std::unordered_map<uintptr_t, WsTag> g_tags;
+
+void remember_ws(const void *ws, const WsTag &tag)
+{
+    std::lock_guard<std::mutex> lock(g_tags_mu);
+    g_tags[reinterpret_cast<uintptr_t>(ws)] = tag;
+}
+
+// precision < 0: any precision
+bcf_status check_ws(const void *ws, int precision, uint32_t n_materials, uint64_t hash, const char *prepared_by)
+{
+    WsTag tag;
+    {
+        std::lock_guard<std::mutex> lock(g_tags_mu);
+        const auto it = g_tags.find(reinterpret_cast<uintptr_t>(ws));
+        if (it == g_tags.end())
+            return fail(BCF_ERR_INVALID_ARG, "workspace %p was not filled by %s", ws, prepared_by);
+        tag = it->second;
+    }
+    if (tag.n_materials != n_materials || tag.hash != hash)
+        return fail(BCF_ERR_INVALID_ARG,
+                    "workspace %p was prepared for another material (or batch): prepare it again for this one", ws);
+    if (precision >= 0 && tag.precision != precision)
+        return fail(BCF_ERR_INVALID_ARG, "workspace %p was prepared for precision %d, called with %d", ws,
+                    tag.precision, precision);
+    return BCF_OK;
+}
+
+bcf::WsHeader ws_header(int precision, uint32_t n_materials, uint64_t hash, size_t scratch_off,
+                        size_t scratch_bytes, size_t total)
+{
+    bcf::WsHeader h;
+    std::memset(&h, 0, sizeof h);
+    h.magic = bcf::kWsMagic;
+    h.abi_version = BCF_ABI_VERSION;
+    h.precision = (uint32_t)precision;
+    h.n_materials = n_materials;
+    h.layout_hash = hash;
+    h.scratch_off = scratch_off;
+    h.scratch_bytes = scratch_bytes;
+    h.total_bytes = total;
+    return h;
+}
+
 // 8-byte units of a material's texel scratch
 size_t scratch_texels(const bcf::MaterialDesc &d)
 {
@@ -245,7 +338,7 @@ bcf_status decode_args(const bcf_material *m, bcf_precision p, const void *ws, c
     if (!queries || !aligned(queries, 4)) return fail(BCF_ERR_INVALID_ARG, "queries NULL or misaligned");
     if (!out || !aligned(out, 4)) return fail(BCF_ERR_INVALID_ARG, "out NULL or misaligned");
     if (n > (size_t)1 << 40) return fail(BCF_ERR_UNSUPPORTED, "n = %zu too large", n);
-    return BCF_OK;
+    return check_ws(ws, (int)p, 1u, material_hash(kFnvOffset, m, p), "bcf_prepare");
 }
 
 uint2 *scratch_of(void *ws, const bcf::WsLayout &lay)
@@ -405,6 +498,13 @@ bcf_status describe_batch(const bcf_material *mats, uint32_t n_mats, bcf_precisi
     return BCF_OK;
 }
 
+uint64_t batch_hash(const bcf_material *mats, uint32_t n_mats, bcf_precision p)
+{
+    uint64_t h = fnv_val(kFnvOffset, n_mats);
+    for (uint32_t k = 0; k < n_mats; ++k) h = material_hash(h, &mats[k], p);
+    return h;
+}
+
 }  // namespace
 
 extern "C" {
@@ -441,9 +541,13 @@ bcf_status bcf_prepare(const bcf_material *m, bcf_precision p, void *ws, size_t 
         return fail(BCF_ERR_INVALID_ARG, "BCF_FP8 needs act_absmax (see bcf_calibrate)");
     if (m->act_absmax && !aligned(m->act_absmax, 4))
         return fail(BCF_ERR_INVALID_ARG, "act_absmax not 4-byte aligned");
-    return device_status(bcf::launch_prepare_weights(m->params, m->act_absmax, sh, kind, lay, ws,
-                                                     static_cast<hipStream_t>(stream)),
-                         "prepare launch");
+    const uint64_t hash = material_hash(kFnvOffset, m, p);
+    const bcf::WsHeader header = ws_header(p, 1, hash, lay.scratch_off, lay.scratch_bytes, lay.total);
+    st = device_status(bcf::launch_prepare_weights(m->params, m->act_absmax, sh, kind, lay, ws, &header,
+                                                   static_cast<hipStream_t>(stream)),
+                       "prepare launch");
+    if (st == BCF_OK) remember_ws(ws, WsTag{(int)p, 1u, hash});
+    return st;
 }
 
 
@@ -470,7 +574,17 @@ bcf_status bcf_unpack(const bcf_material *m, void *ws, void *stream)
     bcf_status st = describe(m, &d, &sh);
     if (st != BCF_OK) return st;
     if (!ws || !aligned(ws, 256)) return fail(BCF_ERR_INVALID_ARG, "workspace NULL or not 256-byte aligned");
-    // the scratch sits at the same offset in every precision's layout
+    // any precision: the scratch sits at the same offset in every precision's layout
+    {
+        std::lock_guard<std::mutex> lock(g_tags_mu);
+        const auto it = g_tags.find(reinterpret_cast<uintptr_t>(ws));
+        if (it == g_tags.end())
+            return fail(BCF_ERR_INVALID_ARG, "workspace %p was not filled by bcf_prepare", ws);
+        if (it->second.n_materials != 1 ||
+            it->second.hash != material_hash(kFnvOffset, m, (bcf_precision)it->second.precision))
+            return fail(BCF_ERR_INVALID_ARG,
+                        "workspace %p was prepared for another material: prepare it again for this one", ws);
+    }
     const bcf::WsLayout lay = layout(d, sh, bcf::MLP_VALU_F32);
     return unpack(d, lay, ws, static_cast<hipStream_t>(stream));
 }
@@ -500,6 +614,8 @@ bcf_status bcf_calibrate(const bcf_material *m, void *ws, const float *queries, 
     if (!act_absmax || !aligned(act_absmax, 4)) return fail(BCF_ERR_INVALID_ARG, "act_absmax NULL or misaligned");
     if (n > 0 && (!queries || !aligned(queries, 4)))
         return fail(BCF_ERR_INVALID_ARG, "queries NULL or misaligned");
+    if ((st = check_ws(ws, BCF_FP32, 1u, material_hash(kFnvOffset, m, BCF_FP32), "bcf_prepare")) != BCF_OK)
+        return st;
     const bcf::WsLayout lay = layout(d, sh, bcf::MLP_VALU_F32);
     hipStream_t s = static_cast<hipStream_t>(stream);
     st = unpack(d, lay, ws, s);
@@ -587,12 +703,17 @@ bcf_status bcf_prepare_batch(const bcf_material *mats, uint32_t n_mats, bcf_prec
     hipStream_t s = static_cast<hipStream_t>(stream);
     for (uint32_t k = 0; k < n_mats; ++k) {
         st = device_status(bcf::launch_prepare_weights(mats[k].params, nullptr, b.sh, b.kind, b.rel,
-                                                       static_cast<uint8_t *>(ws) + b.slots[k].weights_off, s),
+                                                       static_cast<uint8_t *>(ws) + b.slots[k].weights_off,
+                                                       nullptr, s),
                            "prepare launch");
         if (st != BCF_OK) return st;
     }
-    return device_status(bcf::write_batch_table(b.descs.data(), b.slots.data(), n_mats, b.sh.out, ws, b.table_off, s),
-                         "material table copy");
+    const uint64_t hash = batch_hash(mats, n_mats, p);
+    st = device_status(bcf::write_batch_table(b.descs.data(), b.slots.data(), n_mats, b.sh.out,
+                                              ws_header(p, n_mats, hash, 0, 0, b.total), ws, b.table_off, s),
+                       "material table copy");
+    if (st == BCF_OK) remember_ws(ws, WsTag{(int)p, n_mats, hash});
+    return st;
 }
 
 bcf_status bcf_unpack_batch(const bcf_material *mats, uint32_t n_mats, void *ws, void *stream)
@@ -601,6 +722,9 @@ bcf_status bcf_unpack_batch(const bcf_material *mats, uint32_t n_mats, void *ws,
     bcf_status st = describe_batch(mats, n_mats, BCF_FP16, &b);
     if (st != BCF_OK) return st;
     if (!ws || !aligned(ws, 256)) return fail(BCF_ERR_INVALID_ARG, "workspace NULL or not 256-byte aligned");
+    // either batch precision: the texel scratch layout is the same (and so is the hash)
+    if ((st = check_ws(ws, -1, n_mats, batch_hash(mats, n_mats, BCF_FP16), "bcf_prepare_batch")) != BCF_OK)
+        return st;
     for (uint32_t k = 0; k < n_mats; ++k) {
         uint2 *texels = reinterpret_cast<uint2 *>(static_cast<uint8_t *>(ws) + b.slots[k].scratch_off);
         st = device_status(bcf::launch_predecode(b.descs[k], predecode_plan(b.descs[k]), texels,
@@ -622,7 +746,7 @@ bcf_status batch_args(const bcf_material *mats, uint32_t n_mats, bcf_precision p
     if (!offsets || !aligned(offsets, 4)) return fail(BCF_ERR_INVALID_ARG, "offsets NULL or misaligned");
     if (n_total > 0 && (!queries || !aligned(queries, 4) || !out || !aligned(out, 4)))
         return fail(BCF_ERR_INVALID_ARG, "queries or out NULL or misaligned");
-    return BCF_OK;
+    return check_ws(ws, (int)p, n_mats, batch_hash(mats, n_mats, p), "bcf_prepare_batch");
 }
 
 unsigned default_workgroups(uint32_t n_total)

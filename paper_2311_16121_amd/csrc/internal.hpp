@@ -79,8 +79,24 @@ hipError_t launch_predecode(const MaterialDesc &m, const PredecodePlan &p, uint2
 size_t mlp_layer_elems(const MlpShape &s, uint32_t l, MlpKind k);
 uint32_t mlp_layer_rows(const MlpShape &s, uint32_t l, MlpKind k);
 
+// The first 256 bytes of a decode or batch workspace: what it was prepared
+// for, so that a workspace describes itself (the host keeps the same tag per
+// workspace address to validate later calls without reading device memory).
+struct WsHeader {
+    uint32_t magic;                 // kWsMagic
+    uint32_t abi_version;
+    uint32_t precision;             // bcf_precision
+    uint32_t n_materials;           // 1 for a single-material workspace
+    uint64_t layout_hash;           // the material(s) and precision it was prepared for
+    uint64_t scratch_off, scratch_bytes;    // texel scratch (single material)
+    uint64_t total_bytes;
+};
+constexpr uint32_t kWsMagic = 0x57464342u;   // "BCFW"
+
+// header: written to the workspace's first bytes by the same launch (NULL: not written)
 hipError_t launch_prepare_weights(const float *params, const float *act_absmax, const MlpShape &sh,
-                                  MlpKind kind, const WsLayout &lay, void *ws, hipStream_t s);
+                                  MlpKind kind, const WsLayout &lay, void *ws, const WsHeader *header,
+                                  hipStream_t s);
 
 hipError_t launch_calibrate(const MaterialDesc &m, const MlpShape &sh, const WsLayout &lay, const void *ws,
                             const float *queries, size_t n, float *absmax, hipStream_t s);
@@ -99,8 +115,9 @@ struct BatchSlot {
 
 size_t batch_table_bytes(uint32_t n_mats);
 // builds the per-material table and copies it into the workspace (synchronises s)
+// (and the header into the workspace's first bytes, table_off >= sizeof(WsHeader))
 hipError_t write_batch_table(const MaterialDesc *mats, const BatchSlot *slots, uint32_t n_mats, uint32_t out_dim,
-                             void *ws, size_t table_off, hipStream_t s);
+                             const WsHeader &header, void *ws, size_t table_off, hipStream_t s);
 // rel: the weight layout relative to a material's weights_off
 hipError_t launch_batch(void *ws, size_t table_off, size_t items_off, const WsLayout &rel, const MlpShape &sh,
                         MlpKind kind, const float *queries, const uint32_t *offsets, uint32_t n_mats,

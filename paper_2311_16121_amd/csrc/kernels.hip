@@ -274,6 +274,8 @@ struct PrepareArgs {
     MlpKind kind;
     WsLayout lay;
     uint8_t *ws;
+    WsHeader header;
+    uint32_t write_header;
 };
 
 __device__ inline size_t param_offset(const MlpShape &sh, uint32_t l)
@@ -364,12 +366,18 @@ __global__ void k_prepare(PrepareArgs a)
         }
         for (uint32_t o = tid; o < rows; o += stride) bdst[o] = param_b(a, l, o);
     }
+    if (a.write_header && tid == 0) *reinterpret_cast<WsHeader *>(a.ws) = a.header;
 }
 
 hipError_t launch_prepare_weights(const float *params, const float *act_absmax, const MlpShape &sh,
-                                  MlpKind kind, const WsLayout &lay, void *ws, hipStream_t s)
+                                  MlpKind kind, const WsLayout &lay, void *ws, const WsHeader *header,
+                                  hipStream_t s)
 {
-    PrepareArgs a{params, act_absmax, sh, kind, lay, static_cast<uint8_t *>(ws)};
+    PrepareArgs a{params, act_absmax, sh, kind, lay, static_cast<uint8_t *>(ws), {}, 0u};
+    if (header) {
+        a.header = *header;
+        a.write_header = 1;
+    }
     if (kind == MLP_MFMA_FP8) {
         k_fp8_scales<<<sh.n_hidden + 1, 256, 0, s>>>(a);
         const hipError_t e = hipGetLastError();
@@ -509,9 +517,12 @@ __global__ void k_batch_items(BatchArgs a)
 }
 
 hipError_t write_batch_table(const MaterialDesc *mats, const BatchSlot *slots, uint32_t n_mats, uint32_t out_dim,
-                             void *ws, size_t table_off, hipStream_t s)
+                             const WsHeader &header, void *ws, size_t table_off, hipStream_t s)
 {
-    std::vector<BatchMat> table(n_mats);
+    // the header at byte 0, then (from table_off) the material table: one copy
+    std::vector<uint8_t> host(table_off + sizeof(BatchMat) * n_mats, 0);
+    std::memcpy(host.data(), &header, sizeof header);
+    BatchMat *table = reinterpret_cast<BatchMat *>(host.data() + table_off);
     for (uint32_t k = 0; k < n_mats; ++k) {
         WsLayout lay;
         std::memset(&lay, 0, sizeof lay);
@@ -529,8 +540,7 @@ hipError_t write_batch_table(const MaterialDesc *mats, const BatchSlot *slots, u
         b.shared = shared ? 1u : 0u;
         b.interleaved = mats[k].interleaved;
     }
-    hipError_t e = hipMemcpyAsync(static_cast<uint8_t *>(ws) + table_off, table.data(), sizeof(BatchMat) * n_mats,
-                                  hipMemcpyHostToDevice, s);
+    hipError_t e = hipMemcpyAsync(ws, host.data(), host.size(), hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return e;
     return hipStreamSynchronize(s);           // the host table goes out of scope
 }

@@ -237,3 +237,28 @@ def test_batch_validation(bcf):
                                     C.c_void_p(FAKE), None, None) == 1
     assert bcf.lib.bcf_prepare_batch(arr, 2, 1, C.c_void_p(FAKE), 100, None) == 1
     assert "workspace" in bcf.lib.bcf_last_error().decode()
+
+
+def test_workspace_not_filled_by_prepare_is_rejected(bcf):
+    # The library remembers, per workspace address, what bcf_prepare filled it
+    # for; an address it never prepared is an argument error, found on the
+    # host before any launch.
+    m = material(bcf)
+    ws = C.c_void_p(FAKE + (1 << 16))
+    calls = [
+        ("bcf_decode", lambda: bcf.lib.bcf_decode(C.byref(m), 1, ws, C.c_void_p(FAKE), 5, 0, C.c_void_p(FAKE), None)),
+        ("bcf_decode_unpacked", lambda: bcf.lib.bcf_decode_unpacked(C.byref(m), 1, ws, C.c_void_p(FAKE), 5, 0,
+                                                                    C.c_void_p(FAKE), None)),
+        ("bcf_unpack", lambda: bcf.lib.bcf_unpack(C.byref(m), ws, None)),
+        ("bcf_calibrate", lambda: bcf.lib.bcf_calibrate(C.byref(m), ws, C.c_void_p(FAKE), 5, C.c_void_p(FAKE), None)),
+    ]
+    for name, call in calls:
+        assert call() == 1, name
+        assert "not filled by bcf_prepare" in bcf.lib.bcf_last_error().decode(), name
+    from paper_2311_16121_amd._lib import _Material
+    arr = (_Material * 2)(material(bcf), material(bcf, res=(64, 16), levels=5))
+    assert bcf.lib.bcf_unpack_batch(arr, 2, ws, None) == 1
+    assert "not filled by bcf_prepare_batch" in bcf.lib.bcf_last_error().decode()
+    assert bcf.lib.bcf_decode_batch(arr, 2, 1, ws, C.c_void_p(FAKE), C.c_void_p(FAKE), 10,
+                                    C.c_void_p(FAKE), None, None) == 1
+    assert "not filled by bcf_prepare_batch" in bcf.lib.bcf_last_error().decode()

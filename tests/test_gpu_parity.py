@@ -285,6 +285,30 @@ def test_unpack_then_decode_unpacked_equals_decode(bcf):
     assert np.abs(got - oracle.decode(host, q)).max() <= 2e-3
 
 
+def test_workspace_prepared_for_another_precision_or_material_is_rejected(bcf):
+    # bcf_prepare tags the workspace (host record and device header): a
+    # decode at another precision, or of another material, is an argument
+    # error before any launch
+    texs, sizes, lv, params, bias, host = make(32, 6, (12, 16, 9), "B", seed=23)
+    mat = bcf.Material.from_host(texs, sizes, lv, (12, 16, 9), params, bias)
+    other = bcf.Material.from_host(texs, sizes, lv, (12, 16, 9), params, bias)   # same geometry, other buffers
+    qd = dev(synth.uniform_queries(100, synth.rng(24), 5.0))
+    ws = bcf.prepare(mat, bcf.Precision.FP16)
+    header = ws[:48].cpu().numpy()
+    assert bytes(header[:4]) == b"BCFW" and header[8:12].view(np.uint32)[0] == int(bcf.Precision.FP16)
+    bcf.decode(mat, ws, qd, bcf.Precision.FP16)
+    with pytest.raises(bcf.BcfError, match="precision"):
+        bcf.decode(mat, ws, qd, bcf.Precision.FP32)
+    with pytest.raises(bcf.BcfError, match="another material"):
+        bcf.decode(other, ws, qd, bcf.Precision.FP16)
+    with pytest.raises(bcf.BcfError, match="another material"):
+        bcf.unpack(other, ws)
+    # preparing again re-tags it
+    ws2 = bcf.prepare(other, bcf.Precision.FP32)
+    a = bcf.decode(other, ws2, qd, bcf.Precision.FP32).cpu().numpy()
+    assert np.abs(a - oracle.decode(host, qd.cpu().numpy())).max() <= 1e-5
+
+
 @pytest.mark.parametrize("dims", [(12, 32, 32, 10), (12, 16, 9)])
 def test_grid_width_does_not_change_results(bcf, dims):
     # 16x4 tiles over images with ragged right and bottom edges, widths that
