@@ -141,6 +141,26 @@ bcf_status bcf_decode(const bcf_material *m, bcf_precision p, void *ws,
                       const float *queries, size_t n, uint32_t grid_width,
                       float *out, void *stream);
 
+/* bcf_decode for callers that cannot allocate device memory -- code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation --
+ * and so cannot provide the workspace bcf_prepare fills. The library holds
+ * the workspace itself: one 64 MiB array per GPU (BCF_NOALLOC_BYTES), in
+ * device memory the library's code object reserves when it is loaded and
+ * keeps until the process ends. Each call prepares the MLP weights for `p`
+ * into it, unpacks the material's blocks into it and decodes, on `stream`
+ * (which must belong to the current device); queries, n, grid_width and out
+ * as in bcf_decode. No call allocates or frees memory (the first call on a
+ * device looks up the array's device address once).
+ * Returns BCF_ERR_UNSUPPORTED, before any launch, for a material whose
+ * workspace (texel scratch and MLP operands, the size bcf_prepare reports)
+ * exceeds BCF_NOALLOC_BYTES -- up to four 1024 x 1024 pyramids with full
+ * chains fit. All calls on one GPU share its array and leave their data in
+ * it: calls that overlap in time on one GPU (other streams, other threads)
+ * race and give undefined results; order them on one stream. */
+#define BCF_NOALLOC_BYTES ((size_t)64 << 20)
+bcf_status bcf_decode_noalloc(const bcf_material *m, bcf_precision p, const float *queries, size_t n,
+                              uint32_t grid_width, float *out, void *stream);
+
 /* First half of bcf_decode: unpacks every BC6H block of every level of every
  * pyramid (Section 4.2, eqs. (6)-(8) in the format's integer form) into the
  * texel scratch of ws (device, prepared for this material at any precision;

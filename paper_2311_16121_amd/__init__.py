@@ -6,9 +6,10 @@ concatenate, and run the decoder MLP (eq. 3) -- all in HIP kernels behind
 the C ABI of include/bcf.h. This package is the thin Python binding.
 """
 from ._lib import (ABI_VERSION, EXPORTED, BcfError, Batch, Material, Precision, TrainGeometry, abi_version,
-                   calibrate, decode, decode_blocks, decode_unpacked, lib, prepare, texture_bytes,
+                   calibrate, decode, decode_blocks, decode_noalloc, decode_unpacked, lib, prepare, texture_bytes,
                    train_backward, train_decode, train_forward, unpack, workspace_bytes)
 
 __all__ = ["ABI_VERSION", "EXPORTED", "BcfError", "Batch", "Material", "Precision", "TrainGeometry", "abi_version",
-           "calibrate", "decode", "decode_blocks", "decode_unpacked", "lib", "prepare", "texture_bytes",
+           "calibrate", "decode", "decode_blocks", "decode_noalloc", "decode_unpacked", "lib", "prepare",
+           "texture_bytes",
            "train_backward", "train_decode", "train_forward", "unpack", "workspace_bytes"]

@@ -96,6 +96,9 @@ def _load():
     L.bcf_train_backward.argtypes = [C.POINTER(_TrainMaterial), C.c_void_p, C.c_void_p, C.c_size_t,
                                      C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                                      C.c_void_p, C.c_void_p]
+    L.bcf_decode_noalloc.restype = C.c_int
+    L.bcf_decode_noalloc.argtypes = [C.POINTER(_Material), C.c_int, C.c_void_p, C.c_size_t, C.c_uint32,
+                                     C.c_void_p, C.c_void_p]
     L.bcf_decode_blocks.restype = C.c_int
     L.bcf_decode_blocks.argtypes = [C.c_void_p, C.c_size_t, C.c_uint32, C.c_void_p, C.c_void_p]
     if L.bcf_abi_version() != ABI_VERSION:
@@ -107,6 +110,7 @@ lib = _load()
 
 EXPORTED = ("bcf_abi_version", "bcf_last_error", "bcf_texture_bytes", "bcf_prepare",
             "bcf_decode", "bcf_unpack", "bcf_decode_unpacked", "bcf_calibrate", "bcf_decode_blocks",
+            "bcf_decode_noalloc",
             "bcf_batch_workspace_size", "bcf_prepare_batch", "bcf_unpack_batch", "bcf_decode_batch",
             "bcf_tune_batch", "bcf_train_workspace_size", "bcf_train_forward", "bcf_train_backward")
 
@@ -232,6 +236,18 @@ def decode(mat: Material, ws, queries, precision=Precision.FP32, grid_width: int
     _check(lib.bcf_decode(C.byref(mat.c), int(precision), C.c_void_p(ws.data_ptr()),
                           C.c_void_p(q.data_ptr()), q.shape[0], grid_width, C.c_void_p(out.data_ptr()),
                           _stream(stream)), "bcf_decode")
+    return out
+
+
+def decode_noalloc(mat: Material, queries, precision=Precision.FP32, grid_width: int = 0, out=None,
+                   stream=None):
+    """decode() in the library's own per-GPU workspace (bcf_decode_noalloc):
+    no workspace argument, nothing allocated by the library; `out` may be
+    passed so that nothing is allocated here either."""
+    q = _queries(queries)
+    out = _out(mat, q, out)
+    _check(lib.bcf_decode_noalloc(C.byref(mat.c), int(precision), C.c_void_p(q.data_ptr()), q.shape[0],
+                                  grid_width, C.c_void_p(out.data_ptr()), _stream(stream)), "bcf_decode_noalloc")
     return out
 
 

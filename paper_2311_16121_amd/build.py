@@ -20,7 +20,7 @@ OBJDIR = os.path.join(PKG, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["kernels.hip", "frame_f32.hip", "frame_f16.hip", "frame_bf16.hip", "frame_fp8.hip",
-           "frame_f32_mfma.hip", "calibrate.hip", "train.hip", "api.cpp"]
+           "frame_f32_mfma.hip", "calibrate.hip", "train.hip", "noalloc.hip", "api.cpp"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
     # keep the compiler from forming packed fp32 VALU instructions

@@ -623,6 +623,42 @@ bcf_status bcf_calibrate(const bcf_material *m, void *ws, const float *queries, 
     return device_status(bcf::launch_calibrate(d, sh, lay, ws, queries, n, act_absmax, s), "calibrate launch");
 }
 
+bcf_status bcf_decode_noalloc(const bcf_material *m, bcf_precision p, const float *queries, size_t n,
+                              uint32_t grid_width, float *out, void *stream)
+{
+    bcf::MaterialDesc d;
+    bcf::MlpShape sh;
+    bcf::MlpKind kind;
+    bcf_status st = describe(m, &d, &sh);
+    if (st != BCF_OK) return st;
+    if (!kind_of(p, &kind)) return fail(BCF_ERR_UNSUPPORTED, "precision %d not supported", (int)p);
+    if (n == 0) return BCF_OK;
+    if (!queries || !aligned(queries, 4)) return fail(BCF_ERR_INVALID_ARG, "queries NULL or misaligned");
+    if (!out || !aligned(out, 4)) return fail(BCF_ERR_INVALID_ARG, "out NULL or misaligned");
+    if (n > (size_t)1 << 40) return fail(BCF_ERR_UNSUPPORTED, "n = %zu too large", n);
+    if (kind == bcf::MLP_MFMA_FP8 && !m->act_absmax)
+        return fail(BCF_ERR_INVALID_ARG, "BCF_FP8 needs act_absmax (see bcf_calibrate)");
+    if (m->act_absmax && !aligned(m->act_absmax, 4))
+        return fail(BCF_ERR_INVALID_ARG, "act_absmax not 4-byte aligned");
+    const bcf::WsLayout lay = layout(d, sh, kind);
+    if (lay.total > bcf::kNoAllocBytes)
+        return fail(BCF_ERR_UNSUPPORTED,
+                    "bcf_decode_noalloc: this material needs a %zu-byte workspace, the library's own holds %zu "
+                    "(use bcf_prepare and bcf_decode with a caller workspace)",
+                    lay.total, bcf::kNoAllocBytes);
+    void *ws = nullptr;
+    if ((st = device_status(bcf::noalloc_workspace(&ws), "library workspace lookup")) != BCF_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const bcf::WsHeader header = ws_header(p, 1, material_hash(kFnvOffset, m, p), lay.scratch_off,
+                                           lay.scratch_bytes, lay.total);
+    st = device_status(bcf::launch_prepare_weights(m->params, m->act_absmax, sh, kind, lay, ws, &header, s),
+                       "prepare launch");
+    if (st != BCF_OK) return st;
+    if ((st = unpack(d, lay, ws, s)) != BCF_OK) return st;
+    return device_status(bcf::launch_filter_mlp(d, sh, kind, lay, ws, queries, n, grid_width, out, s),
+                         "decode launch");
+}
+
 bcf_status bcf_decode_blocks(const void *blocks, size_t n_blocks, uint32_t is_signed, uint16_t *halves,
                              void *stream)
 {

@@ -60,6 +60,12 @@ struct WsLayout {
     size_t total;
 };
 
+// The workspace bcf_decode_noalloc uses: a file-scope device array of
+// kNoAllocBytes (noalloc.hip), one per GPU, held until the process ends.
+constexpr size_t kNoAllocBytes = (size_t)64 << 20;
+// its device address on the current device (looked up on the first call per device)
+hipError_t noalloc_workspace(void **ptr);
+
 // Kernel-side launchers (kernels.hip)
 hipError_t launch_decode_blocks(const uint4 *blocks, size_t n, uint32_t is_signed, uint16_t *out,
                                 hipStream_t s);

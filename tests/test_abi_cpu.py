@@ -262,3 +262,17 @@ def test_workspace_not_filled_by_prepare_is_rejected(bcf):
     assert bcf.lib.bcf_decode_batch(arr, 2, 1, ws, C.c_void_p(FAKE), C.c_void_p(FAKE), 10,
                                     C.c_void_p(FAKE), None, None) == 1
     assert "not filled by bcf_prepare_batch" in bcf.lib.bcf_last_error().decode()
+
+
+def test_noalloc_refuses_oversized_materials_and_bad_arguments_before_any_launch(bcf):
+    big = material(bcf, res=2048, levels=12, dims=(12, 32, 32, 10))
+    assert bcf.lib.bcf_decode_noalloc(C.byref(big), 1, C.c_void_p(FAKE), 5, 0, C.c_void_p(FAKE), None) == 2
+    err = bcf.lib.bcf_last_error().decode()
+    assert "workspace" in err and str(64 << 20) in err
+    m = material(bcf)
+    assert bcf.lib.bcf_decode_noalloc(C.byref(m), 1, None, 0, 0, None, None) == 0          # n == 0: no-op
+    assert bcf.lib.bcf_decode_noalloc(C.byref(m), 1, None, 5, 0, C.c_void_p(FAKE), None) == 1
+    assert bcf.lib.bcf_decode_noalloc(C.byref(m), 1, C.c_void_p(FAKE), 5, 0, None, None) == 1
+    assert bcf.lib.bcf_decode_noalloc(C.byref(m), 3, C.c_void_p(FAKE), 5, 0, C.c_void_p(FAKE), None) == 1
+    assert "act_absmax" in bcf.lib.bcf_last_error().decode()
+    assert bcf.lib.bcf_decode_noalloc(C.byref(m), 99, C.c_void_p(FAKE), 5, 0, C.c_void_p(FAKE), None) == 2
