@@ -292,7 +292,8 @@ def bench_batch(args):
         "config": {"workload": "batch64: 64 materials, base 512..4096^2 (4 pyramids, full chains), MLP 12-32-32-10 "
                                "FP16 per material, queries log-uniform in [2^14, 2^22] per material",
                    "queries": n, "materials": spec.n_materials, "texture_bytes": blocks * 16,
-                   "plan": {"workgroups": plan[0], "interleave": plan[1], "tuned_decode_ms": tuned_ms}},
+                   "plan": {"workgroups": plan[0], "interleave": plan[1], "run": plan[2], "waves": plan[3],
+                            "tuned_decode_ms": tuned_ms}},
         "roofline": {"bound": "hbm", "kernel": "k_batch (fp16)", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(BATCH_TRAFFIC_FILE),

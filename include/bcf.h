@@ -33,7 +33,7 @@
 extern "C" {
 #endif
 
-#define BCF_ABI_VERSION 1
+#define BCF_ABI_VERSION 2
 
 typedef enum {
     BCF_OK = 0,
@@ -215,12 +215,16 @@ bcf_status bcf_decode_blocks(const void *blocks, size_t n_blocks, uint32_t is_si
  * and the tuner, this precision).
  * ------------------------------------------------------------------------ */
 
-/* Launch shape of bcf_decode_batch (bcf_tune_batch picks one). */
+/* Launch shape of bcf_decode_batch (bcf_tune_batch picks one). A work item
+ * is a run of 64 consecutive queries of one material. */
 typedef struct {
-    uint32_t workgroups;   /* persistent workgroups of 256 threads (rounded up to a
-                              multiple of 8); 0 = a default from n_total */
-    uint32_t interleave;   /* 1: the waves on one XCD take interleaved work items;
-                              0: each wave a contiguous range */
+    uint32_t workgroups;   /* persistent workgroups (rounded up to a multiple of 8);
+                              0 = a default from n_total */
+    uint32_t interleave;   /* 1: the waves take interleaved runs of `run` items;
+                              0: each wave one contiguous range of items */
+    uint32_t run;          /* interleaved: consecutive items per wave turn (items of
+                              64 x run queries); 0 means 1 */
+    uint32_t waves;        /* waves per workgroup: 2 or 4 (0 means 4) */
 } bcf_batch_plan;
 
 /* Workspace bytes for the batch (256-byte aligned start). */
@@ -233,7 +237,9 @@ bcf_status bcf_batch_workspace_size(const bcf_material *mats, uint32_t n_mats, b
 bcf_status bcf_prepare_batch(const bcf_material *mats, uint32_t n_mats, bcf_precision p, void *ws,
                              size_t ws_bytes, void *stream);
 
-/* bcf_unpack for every material of the batch (one launch per material).
+/* bcf_unpack for every material of the batch, in one launch (each workgroup
+ * unpacks one 256-lane chunk of a table of every material's (pyramid, level)
+ * segments that bcf_prepare_batch wrote into the workspace).
  * A material whose four pyramids share size, level count and bias keeps its
  * texels position-interleaved in the batch workspace (the four pyramids'
  * texels of one position together), so a decode reads one footprint row of
@@ -249,8 +255,10 @@ bcf_status bcf_decode_batch(const bcf_material *mats, uint32_t n_mats, bcf_preci
                             float *out, const bcf_batch_plan *plan, void *stream);
 
 /* Autotuner: runs bcf_decode_batch over a set of launch shapes on these
- * inputs, timing each with events, and returns the fastest in *best (and its
- * time in *best_ms when not NULL). Synchronises `stream`; out is overwritten. */
+ * inputs -- workgroup counts, 2 or 4 waves per workgroup, contiguous ranges
+ * or interleaved runs of 1, 2 or 4 items (64, 128 or 256 queries) -- timing
+ * each with events, and returns the fastest in *best (and its time in
+ * *best_ms when not NULL). Synchronises `stream`; out is overwritten. */
 bcf_status bcf_tune_batch(const bcf_material *mats, uint32_t n_mats, bcf_precision p, void *ws,
                           const float *queries, const uint32_t *offsets, uint32_t n_total,
                           float *out, bcf_batch_plan *best, float *best_ms, void *stream);

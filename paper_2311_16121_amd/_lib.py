@@ -12,7 +12,7 @@ import os
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIBRARY = os.path.join(PKG, "libbcf.so")
-ABI_VERSION = 1
+ABI_VERSION = 2
 
 
 class Precision(enum.IntEnum):
@@ -39,7 +39,8 @@ class _Material(C.Structure):
 
 
 class _BatchPlan(C.Structure):
-    _fields_ = [("workgroups", C.c_uint32), ("interleave", C.c_uint32)]
+    _fields_ = [("workgroups", C.c_uint32), ("interleave", C.c_uint32), ("run", C.c_uint32),
+                ("waves", C.c_uint32)]
 
 
 class _TrainTexture(C.Structure):
@@ -346,7 +347,9 @@ class Batch:
         return out
 
     def tune(self, queries, offsets, out=None, stream=None):
-        """Times the candidate launch shapes; returns ((workgroups, interleave), ms)."""
+        """Times the candidate launch shapes; returns ((workgroups, interleave,
+        run, waves), ms). A plan for decode() is such a tuple (trailing
+        entries may be left out: run 1, waves 4)."""
         import torch
         q = _queries(queries)
         offs = self._offsets(offsets)
@@ -358,7 +361,7 @@ class Batch:
                                   C.c_void_p(q.data_ptr()), C.c_void_p(offs.data_ptr()), q.shape[0],
                                   C.c_void_p(out.data_ptr()), C.byref(best), C.byref(ms), _stream(stream)),
                "bcf_tune_batch")
-        return (best.workgroups, best.interleave), ms.value
+        return (best.workgroups, best.interleave, best.run, best.waves), ms.value
 
 
 # ---------------------------------------------------------------------------

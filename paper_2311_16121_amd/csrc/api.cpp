@@ -444,10 +444,11 @@ bcf_status bind_train_ws(bcf::TrainDesc *d, void *ws)
 }
 
 // A batch: every material valid, one MLP shape; the workspace holds a 256-byte
-// header, the material table, the item prefix, then per material its texel
-// scratch and its MLP operands.
+// header, the material table, the item prefix, the unpack segment table and
+// its chunk map, then per material its texel scratch, then the MLP operands.
 struct BatchLayout {
-    size_t table_off, items_off, total;
+    size_t table_off, items_off, segs_off, chunk_seg_off, total;
+    uint32_t n_seg, n_chunks;               // unpack segments of every material, their chunks of 256 lanes
     std::vector<bcf::BatchSlot> slots;
     std::vector<bcf::MaterialDesc> descs;
     bcf::MlpShape sh;
@@ -471,6 +472,9 @@ bcf_status describe_batch(const bcf_material *mats, uint32_t n_mats, bcf_precisi
     off = align_up(off + bcf::batch_table_bytes(n_mats), 256);
     b->items_off = off;
     off = align_up(off + (size_t)(n_mats + 1) * 4, 256);
+    b->segs_off = off;                      // its size is known once the materials are described
+    b->n_seg = 0;
+    b->n_chunks = 0;
     for (uint32_t k = 0; k < n_mats; ++k) {
         bcf::MlpShape sh;
         const bcf_status st = describe(&mats[k], &b->descs[k], &sh);
@@ -485,6 +489,14 @@ bcf_status describe_batch(const bcf_material *mats, uint32_t n_mats, bcf_precisi
             return fail(BCF_ERR_INVALID_ARG, "material %u: MLP dims differ from material 0", k);
         }
         interleave_if_shared(b->descs[k]);
+        const bcf::PredecodePlan plan = predecode_plan(b->descs[k]);
+        b->n_seg += plan.n_seg;
+        b->n_chunks += plan.seg_wg[plan.n_seg];
+    }
+    off = align_up(off + sizeof(bcf::UnpackSeg) * b->n_seg, 256);
+    b->chunk_seg_off = off;                 // segment of each unpack chunk
+    off = align_up(off + sizeof(uint32_t) * b->n_chunks, 256);
+    for (uint32_t k = 0; k < n_mats; ++k) {
         b->slots[k].scratch_off = off;
         b->slots[k].scratch_bytes = scratch_texels(b->descs[k]) * 8;
         off = align_up(off + b->slots[k].scratch_bytes, 256);
@@ -744,9 +756,40 @@ bcf_status bcf_prepare_batch(const bcf_material *mats, uint32_t n_mats, bcf_prec
                            "prepare launch");
         if (st != BCF_OK) return st;
     }
+    // the unpack segments of every material, numbered in one sequence of chunks
+    std::vector<bcf::UnpackSeg> segs;
+    std::vector<uint32_t> chunk_seg(b.n_chunks);
+    segs.reserve(b.n_seg);
+    uint32_t chunk0 = 0;
+    for (uint32_t k = 0; k < n_mats; ++k) {
+        const bcf::MaterialDesc &d = b.descs[k];
+        const bcf::PredecodePlan plan = predecode_plan(d);
+        uint2 *texels = reinterpret_cast<uint2 *>(static_cast<uint8_t *>(ws) + b.slots[k].scratch_off);
+        for (uint32_t j = 0; j < plan.n_seg; ++j) {
+            const uint32_t l = plan.seg_lvl[j];
+            const bcf::TexDesc &T0 = d.tex[d.interleaved ? 0u : plan.seg_tex[j]];
+            bcf::UnpackSeg g;
+            std::memset(&g, 0, sizeof g);
+            for (uint32_t t = 0; t < (uint32_t)bcf::kMaxTextures; ++t) {
+                const bcf::TexDesc &T = d.interleaved ? d.tex[t < d.n_tex ? t : 0u] : T0;
+                g.blocks[t] = T.blocks + T.blk_off[l];
+            }
+            g.texels = texels + (d.interleaved ? (size_t)bcf::kMaxTextures : 1u) * T0.tex_off[l];
+            g.lw = level_dim(T0.w, l);
+            g.lh = level_dim(T0.h, l);
+            g.wg0 = chunk0 + plan.seg_wg[j];
+            g.flags = (d.interleaved ? bcf::kSegInterleaved : 0u) | (d.is_signed ? bcf::kSegSigned : 0u);
+            std::fill(chunk_seg.begin() + g.wg0, chunk_seg.begin() + chunk0 + plan.seg_wg[j + 1],
+                      (uint32_t)segs.size());
+            segs.push_back(g);
+        }
+        chunk0 += plan.seg_wg[plan.n_seg];
+    }
     const uint64_t hash = batch_hash(mats, n_mats, p);
     st = device_status(bcf::write_batch_table(b.descs.data(), b.slots.data(), n_mats, b.sh.out,
-                                              ws_header(p, n_mats, hash, 0, 0, b.total), ws, b.table_off, s),
+                                              ws_header(p, n_mats, hash, 0, 0, b.total), ws, b.table_off,
+                                              segs.data(), (uint32_t)segs.size(), b.segs_off, chunk_seg.data(),
+                                              b.n_chunks, b.chunk_seg_off, s),
                        "material table copy");
     if (st == BCF_OK) remember_ws(ws, WsTag{(int)p, n_mats, hash});
     return st;
@@ -761,14 +804,12 @@ bcf_status bcf_unpack_batch(const bcf_material *mats, uint32_t n_mats, void *ws,
     // either batch precision: the texel scratch layout is the same (and so is the hash)
     if ((st = check_ws(ws, -1, n_mats, batch_hash(mats, n_mats, BCF_FP16), "bcf_prepare_batch")) != BCF_OK)
         return st;
-    for (uint32_t k = 0; k < n_mats; ++k) {
-        uint2 *texels = reinterpret_cast<uint2 *>(static_cast<uint8_t *>(ws) + b.slots[k].scratch_off);
-        st = device_status(bcf::launch_predecode(b.descs[k], predecode_plan(b.descs[k]), texels,
-                                                 static_cast<hipStream_t>(stream)),
-                           "unpack launch");
-        if (st != BCF_OK) return st;
-    }
-    return BCF_OK;
+    // one launch over the segment table bcf_prepare_batch wrote
+    const uint8_t *base = static_cast<const uint8_t *>(ws);
+    const bcf::UnpackSeg *segs = reinterpret_cast<const bcf::UnpackSeg *>(base + b.segs_off);
+    const uint32_t *chunk_seg = reinterpret_cast<const uint32_t *>(base + b.chunk_seg_off);
+    return device_status(bcf::launch_predecode_batch(segs, chunk_seg, b.n_chunks, static_cast<hipStream_t>(stream)),
+                         "unpack launch");
 }
 
 namespace {
@@ -797,13 +838,19 @@ bcf_status bcf_decode_batch(const bcf_material *mats, uint32_t n_mats, bcf_preci
                             const float *queries, const uint32_t *offsets, uint32_t n_total, float *out,
                             const bcf_batch_plan *plan, void *stream)
 {
+    if (plan && (plan->waves != 0 && plan->waves != 2 && plan->waves != 4))
+        return fail(BCF_ERR_INVALID_ARG, "plan->waves = %u, expected 0, 2 or 4", plan->waves);
+    if (plan && plan->run > 64) return fail(BCF_ERR_INVALID_ARG, "plan->run = %u, at most 64", plan->run);
     BatchLayout b;
     const bcf_status st = batch_args(mats, n_mats, p, ws, queries, offsets, n_total, out, &b);
     if (st != BCF_OK) return st;
-    const unsigned wg = plan && plan->workgroups ? plan->workgroups : default_workgroups(n_total);
-    const uint32_t inter = plan ? (plan->interleave ? 1u : 0u) : 1u;
+    bcf::BatchShape shape;
+    shape.workgroups = plan && plan->workgroups ? plan->workgroups : default_workgroups(n_total);
+    shape.interleave = plan ? (plan->interleave ? 1u : 0u) : 1u;
+    shape.run = plan && plan->run ? plan->run : 1u;
+    shape.waves = plan && plan->waves ? plan->waves : 4u;
     return device_status(bcf::launch_batch(ws, b.table_off, b.items_off, b.rel, b.sh, b.kind, queries, offsets, n_mats,
-                                           n_total, out, wg, inter, static_cast<hipStream_t>(stream)),
+                                           n_total, out, shape, static_cast<hipStream_t>(stream)),
                          "batch launch");
 }
 
@@ -822,19 +869,24 @@ bcf_status bcf_tune_batch(const bcf_material *mats, uint32_t n_mats, bcf_precisi
         (void)hipEventDestroy(e0);
         return st;
     }
-    static const unsigned kGroups[] = {256, 512, 1024, 2048, 4096};
+    // candidate shapes: total waves from 1024 to 16384 in 2- or 4-wave
+    // workgroups; contiguous ranges, or interleaved runs of 1, 2 or 4 items
+    static const unsigned kWaves[] = {1024, 2048, 4096, 8192, 16384};
+    static const uint32_t kRuns[] = {0, 1, 2, 4};          // 0: contiguous ranges
     float best_t = -1.0f;
-    bcf_batch_plan pick = {default_workgroups(n_total), 1};
-    for (unsigned wg : kGroups) {
-        for (uint32_t inter = 0; inter < 2 && st == BCF_OK; ++inter) {
+    bcf_batch_plan pick = {default_workgroups(n_total), 1, 1, 4};
+    for (unsigned tw : kWaves)
+    for (uint32_t waves = 2; waves <= 4 && st == BCF_OK; waves += 2) {
+        for (uint32_t r = 0; r < 4 && st == BCF_OK; ++r) {
+            const bcf::BatchShape shape{tw / waves, kRuns[r] ? 1u : 0u, kRuns[r] ? kRuns[r] : 1u, waves};
             auto run = [&]() {
                 return device_status(bcf::launch_batch(ws, b.table_off, b.items_off, b.rel, b.sh, b.kind, queries,
-                                                       offsets, n_mats, n_total, out, wg, inter, s),
+                                                       offsets, n_mats, n_total, out, shape, s),
                                      "batch launch");
             };
             if ((st = run()) != BCF_OK) break;                       // warm-up
             (void)hipEventRecord(e0, s);
-            for (int r = 0; r < 3 && st == BCF_OK; ++r) st = run();
+            for (int rep = 0; rep < 3 && st == BCF_OK; ++rep) st = run();
             (void)hipEventRecord(e1, s);
             if (st != BCF_OK || (st = device_status(hipEventSynchronize(e1), "tune sync")) != BCF_OK) break;
             float ms = 0.0f;
@@ -842,8 +894,7 @@ bcf_status bcf_tune_batch(const bcf_material *mats, uint32_t n_mats, bcf_precisi
             ms /= 3.0f;
             if (best_t < 0.0f || ms < best_t) {
                 best_t = ms;
-                pick.workgroups = wg;
-                pick.interleave = inter;
+                pick = bcf_batch_plan{shape.workgroups, shape.interleave, shape.run, shape.waves};
             }
         }
         if (st != BCF_OK) break;

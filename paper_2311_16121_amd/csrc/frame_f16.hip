@@ -9,9 +9,9 @@ hipError_t launch_frame_f16(const FrameArgs &a, const MlpShape &sh, bool shared,
                   : launch_frame_kind<MLP_MFMA_F16, 16, false>(a, sh, s);
 }
 
-hipError_t launch_batch_f16(const BatchArgs &a, const MlpShape &sh, unsigned grid, hipStream_t s)
+hipError_t launch_batch_f16(const BatchArgs &a, const MlpShape &sh, unsigned grid, uint32_t waves, hipStream_t s)
 {
-    return launch_batch_kind<MLP_MFMA_F16, 16>(a, sh, grid, s);
+    return launch_batch_kind<MLP_MFMA_F16, 16>(a, sh, grid, waves, s);
 }
 
 }  // namespace bcf

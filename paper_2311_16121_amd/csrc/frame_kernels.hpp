@@ -507,7 +507,8 @@ struct BatchArgs {
     const float *queries;
     float *out;
     uint32_t n_mats, n_total, out_dim;
-    uint32_t interleave;                   // 1: waves of an XCD interleave items; 0: contiguous ranges
+    uint32_t interleave;                   // 1: waves interleave runs of items; 0: contiguous ranges
+    uint32_t run;                          // interleaved: consecutive items (of 64 queries) a wave takes
 };
 
 // Query range of material k: the caller's offsets clamped to [0, n_total],
@@ -519,12 +520,13 @@ __device__ __forceinline__ void batch_range(const BatchArgs &a, uint32_t k, uint
     cnt = min(q1 - q0, (uint32_t)kMaxQueriesPerLaunch);
 }
 
-template <MlpKind K, int H, int NH, int C>
-__global__ void __launch_bounds__(kFrameThreads) k_batch(BatchArgs a)
+// W waves per workgroup (the autotuner picks 2 or 4).
+template <MlpKind K, int H, int NH, int C, int W>
+__global__ void __launch_bounds__(64 * W) k_batch(BatchArgs a)
 {
     constexpr bool VALU = K == MLP_VALU_F32;
-    __shared__ LevelLut lut[kFrameWaves];                 // each wave's current material
-    __shared__ float4_t stage[kFrameWaves][64 * kMaxOut / 4];   // features, then output rows
+    __shared__ LevelLut lut[W];                           // each wave's current material
+    __shared__ float4_t stage[W][64 * kMaxOut / 4];       // features, then output rows
     // the wave index is uniform across the wave: say so, so that everything
     // derived from it (work items, materials, offsets) lives in SGPRs
     const uint32_t lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -532,13 +534,16 @@ __global__ void __launch_bounds__(kFrameThreads) k_batch(BatchArgs a)
     float4_t (*feats)[4] = reinterpret_cast<float4_t (*)[4]>(&stage[wv][0]);
     const uint32_t total = a.items[a.n_mats];
 
+    // interleaved: wave g takes runs of `run` consecutive items, g-th run of
+    // every gridDim.x * W; contiguous: the XCD's band split into one range per wave
     ItemRange items;
+    uint32_t run = 1;
     if (a.interleave) {
-        items = ItemRange{blockIdx.x * kFrameWaves + wv, total, gridDim.x * kFrameWaves};
+        run = max(a.run, 1u);
+        items = ItemRange{(blockIdx.x * W + wv) * run, total, gridDim.x * W * run};
     } else {
-        // contiguous: the XCD's band split into one range per wave
         const uint32_t xcd = blockIdx.x % kXcds, local = blockIdx.x / kXcds;
-        const uint32_t waves = (gridDim.x / kXcds) * kFrameWaves, w = local * kFrameWaves + wv;
+        const uint32_t waves = (gridDim.x / kXcds) * W, w = local * W + wv;
         const uint64_t lo = (uint64_t)total * xcd / kXcds, hi = (uint64_t)total * (xcd + 1) / kXcds;
         items.first = (uint32_t)(lo + (hi - lo) * w / waves);
         items.end = (uint32_t)(lo + (hi - lo) * (w + 1) / waves);
@@ -550,7 +555,8 @@ __global__ void __launch_bounds__(kFrameThreads) k_batch(BatchArgs a)
     float lb[2 * kMaxTextures];
     const uint8_t *wbase = a.ws;
     __amdgpu_buffer_rsrc_t rs = make_rsrc(a.ws, 0), rq = rs, ro = rs;
-    for (uint32_t it = items.first; it < items.end; it += items.step) {
+    for (uint32_t it0 = items.first; it0 < items.end; it0 += items.step)
+    for (uint32_t it = it0; it < min(it0 + run, items.end); ++it) {
         // the material: the last k with items[k] <= it (empty materials share
         // their first item with the next one, which the search lands on)
         uint32_t lo = 0, hi = a.n_mats;
@@ -599,11 +605,12 @@ __global__ void __launch_bounds__(kFrameThreads) k_batch(BatchArgs a)
 }
 
 template <MlpKind K, int C>
-hipError_t launch_batch_kind(const BatchArgs &a, const MlpShape &sh, unsigned grid, hipStream_t s)
+hipError_t launch_batch_kind(const BatchArgs &a, const MlpShape &sh, unsigned grid, uint32_t waves, hipStream_t s)
 {
 #define BCF_CASE(H, NH)                                                                       \
     if (sh.hidden == H && sh.n_hidden == NH) {                                               \
-        k_batch<K, H, NH, C><<<grid, kFrameThreads, 0, s>>>(a);                               \
+        if (waves == 2) k_batch<K, H, NH, C, 2><<<grid, 128, 0, s>>>(a);                      \
+        else k_batch<K, H, NH, C, 4><<<grid, 256, 0, s>>>(a);                                 \
         return hipGetLastError();                                                             \
     }
     BCF_CASE(16, 1) BCF_CASE(16, 2) BCF_CASE(16, 3)
@@ -674,7 +681,7 @@ hipError_t launch_frame_fp8(const FrameArgs &a, const MlpShape &sh, bool shared,
 hipError_t launch_frame_f32_mfma(const FrameArgs &a, const MlpShape &sh, bool shared, hipStream_t s);
 hipError_t launch_calibrate_kernel(const FrameArgs &a, const MlpShape &sh, bool shared, unsigned grid,
                                    hipStream_t s);
-hipError_t launch_batch_f16(const BatchArgs &a, const MlpShape &sh, unsigned grid, hipStream_t s);
-hipError_t launch_batch_f32(const BatchArgs &a, const MlpShape &sh, unsigned grid, hipStream_t s);
+hipError_t launch_batch_f16(const BatchArgs &a, const MlpShape &sh, unsigned grid, uint32_t waves, hipStream_t s);
+hipError_t launch_batch_f32(const BatchArgs &a, const MlpShape &sh, unsigned grid, uint32_t waves, hipStream_t s);
 
 }  // namespace bcf

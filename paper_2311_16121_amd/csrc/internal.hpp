@@ -81,6 +81,20 @@ struct PredecodePlan {
 hipError_t launch_predecode(const MaterialDesc &m, const PredecodePlan &p, uint2 *texels,
                             hipStream_t s);
 
+// One segment of an unpack: one level of one pyramid, or of all four
+// pyramids of a position-interleaved scratch.
+constexpr uint32_t kSegInterleaved = 1u, kSegSigned = 2u;
+struct UnpackSeg {
+    const uint4 *blocks[kMaxTextures];  // the level's first block per pyramid slot (slot 0 unless interleaved)
+    uint2 *texels;                      // the level's first texel (interleaved: first position)
+    uint32_t lw, lh;                    // level size in texels
+    uint32_t wg0;                       // the segment's first chunk of 256 lanes in its launch
+    uint32_t flags;                     // kSegInterleaved | kSegSigned
+};
+// every segment of a batch in one launch (segs in device memory, by first chunk)
+// chunk_seg[c] = the segment of chunk c (n_chunks entries)
+hipError_t launch_predecode_batch(const UnpackSeg *segs, const uint32_t *chunk_seg, uint32_t n_chunks, hipStream_t s);
+
 // operand elements and rows of layer l in the workspace (kernels.hip owns the layout)
 size_t mlp_layer_elems(const MlpShape &s, uint32_t l, MlpKind k);
 uint32_t mlp_layer_rows(const MlpShape &s, uint32_t l, MlpKind k);
@@ -121,12 +135,23 @@ struct BatchSlot {
 
 size_t batch_table_bytes(uint32_t n_mats);
 // builds the per-material table and copies it into the workspace (synchronises s)
-// (and the header into the workspace's first bytes, table_off >= sizeof(WsHeader))
+// (and the header into the workspace's first bytes, table_off >= sizeof(WsHeader),
+// the unpack segment table at segs_off, and the chunk map at chunk_seg_off)
 hipError_t write_batch_table(const MaterialDesc *mats, const BatchSlot *slots, uint32_t n_mats, uint32_t out_dim,
-                             const WsHeader &header, void *ws, size_t table_off, hipStream_t s);
+                             const WsHeader &header, void *ws, size_t table_off, const UnpackSeg *segs,
+                             uint32_t n_seg, size_t segs_off, const uint32_t *chunk_seg, uint32_t n_chunks,
+                             size_t chunk_seg_off, hipStream_t s);
+// Launch shape of the batched decode: workgroups, waves per workgroup (2 or
+// 4), and how the waves share the items (runs of 64 queries): interleaved
+// runs of `run` consecutive items, or one contiguous range per wave.
+struct BatchShape {
+    unsigned workgroups;
+    uint32_t interleave, run, waves;
+};
+
 // rel: the weight layout relative to a material's weights_off
 hipError_t launch_batch(void *ws, size_t table_off, size_t items_off, const WsLayout &rel, const MlpShape &sh,
                         MlpKind kind, const float *queries, const uint32_t *offsets, uint32_t n_mats,
-                        uint32_t n_total, float *out, unsigned workgroups, uint32_t interleave, hipStream_t s);
+                        uint32_t n_total, float *out, const BatchShape &shape, hipStream_t s);
 
 }  // namespace bcf

@@ -78,6 +78,15 @@ struct PredecodeArgs {
 };
 
 typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+// Global-memory views of the scratch and of the blocks. Pointers that the
+// batch kernel reads from its segment table are generic to the compiler,
+// which would access them with flat instructions (a flat store also counts
+// against the LDS wait counter, so every LDS read after one waits for the
+// store); these casts keep every access a global one.
+typedef __attribute__((address_space(1))) u32x4_t global_u32x4;
+typedef __attribute__((address_space(1))) const u32x4_t global_block;
+typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) u32x2_t global_texel;
 
 // Two texels to the scratch as one 16-byte non-temporal store: the unpack
 // never reads them back, and the decode that follows it runs faster when the
@@ -85,34 +94,30 @@ typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
 // frame benchmark's unpack-then-decode step).
 __device__ __forceinline__ void store_pair(uint2 *dst, uint2 t0, uint2 t1)
 {
-    __builtin_nontemporal_store((u32x4_t){t0.x, t0.y, t1.x, t1.y}, reinterpret_cast<u32x4_t *>(dst));
+    __builtin_nontemporal_store((u32x4_t){t0.x, t0.y, t1.x, t1.y}, (global_u32x4 *)dst);
 }
 
+// One chunk (256 lanes) of one unpack segment into the texel scratch. The
+// whole workgroup calls it (it synchronises once); `palette` and `slots` are
+// the workgroup's LDS, `table` the mode table.
 template <bool SIGNED>
-__global__ void __launch_bounds__(256) k_predecode(PredecodeArgs a)
+__device__ __forceinline__ void unpack_chunk(const UnpackSeg &sg, uint32_t chunk, const uint32_t *table,
+                                             uint2 (*palette)[256], uint2 *slots)
 {
-    __shared__ uint32_t table[kTableWords];
-    // each lane's block palette, entry-major so that lane L's entries sit in
-    // consecutive 8-byte slots across lanes, and its 16 four-bit slots
-    __shared__ uint2 palette[16][256];
-    __shared__ uint2 slots[256];
-    load_table(table);
-    // segment of this workgroup (uniform scan over at most 64 entries)
-    const uint32_t wg = blockIdx.x;
-    uint32_t seg = 0;
-    while (seg + 1 < a.p.n_seg && a.p.seg_wg[seg + 1] <= wg) ++seg;
-    const uint32_t l = a.p.seg_lvl[seg];
     // interleaved scratch: lane = 4 * block + pyramid, all four pyramids of a
     // level in one segment; otherwise lane = block of the segment's pyramid
-    const uint32_t il = a.m.interleaved;
-    const uint32_t li = (wg - a.p.seg_wg[seg]) * 256 + threadIdx.x;
-    const TexDesc &T = a.m.tex[il ? (li & 3u) : a.p.seg_tex[seg]];
-    const uint32_t lw = max(T.w >> l, 1u), lh = max(T.h >> l, 1u);
+    const uint32_t il = sg.flags & kSegInterleaved;
+    const uint32_t li = chunk * 256 + threadIdx.x;
+    const uint32_t lw = sg.lw, lh = sg.lh;
     const uint32_t bx = (lw + 3) / 4, by = (lh + 3) / 4, n_blk = bx * by;
-    const uint32_t first = (wg - a.p.seg_wg[seg]) * 256;   // this workgroup's first block (per-pyramid layout)
+    const uint32_t first = chunk * 256;         // this chunk's first block (per-pyramid layout)
     const uint32_t bi = il ? li >> 2 : li;
     if (bi < n_blk) {
-        const uint4 b = T.blocks[T.blk_off[l] + bi];
+        // the lane's pyramid by selects (an indexed pointer array would sit
+        // in private memory)
+        const uint32_t pyr = il ? (li & 3u) : 0u;
+        const uint4 *src = pyr == 0 ? sg.blocks[0] : pyr == 1 ? sg.blocks[1] : pyr == 2 ? sg.blocks[2] : sg.blocks[3];
+        const u32x4_t b = ((global_block *)src)[bi];
         Bc6hHeader h;
         bc6h_header<SIGNED>(b.x, b.y, b.z, b.w, table, h);
         uint32_t pal[16][2];
@@ -142,14 +147,14 @@ __global__ void __launch_bounds__(256) k_predecode(PredecodeArgs a)
         // block 8h + L / 8, read through LDS from that block's lanes.
         // Non-temporal like the per-pyramid layout's stores.
         const uint32_t lane = threadIdx.x & 63u, wave0 = threadIdx.x & ~63u;
-        const uint32_t chunk = lane & 7u, pp = 2 * (lane & 1u), cpos = chunk >> 1;
+        const uint32_t chunk8 = lane & 7u, pp = 2 * (lane & 1u), cpos = chunk8 >> 1;
         for (uint32_t h = 0; h < 2; ++h) {
             const uint32_t blw = 8 * h + (lane >> 3);                     // block within the wave
             const uint32_t bj = ((li - lane) >> 2) + blw;                 // its index in the level
             if (bj >= n_blk) continue;
             const uint32_t lb = wave0 + 4 * blw + pp;                     // LDS lane of pyramid pp
             const uint32_t x0 = 4 * (bj % bx), y0 = 4 * (bj / bx);
-            uint2 *dst = a.texels + (size_t)kMaxTextures * T.tex_off[l] + pp;
+            uint2 *dst = sg.texels + pp;
             for (uint32_t r = 0; r < 4; ++r) {
                 if (y0 + r >= lh) break;
                 uint2 *row = dst + (size_t)kMaxTextures * (y0 + r) * pitch;
@@ -165,7 +170,7 @@ __global__ void __launch_bounds__(256) k_predecode(PredecodeArgs a)
         }
         return;
     }
-    uint2 *dst = a.texels + T.tex_off[l];
+    uint2 *dst = sg.texels;
     if (lw >= 4) {
         // A wave's 64 blocks, 32 at a time: lanes 2k and 2k + 1 write the
         // two halves of one block row, so each store instruction covers
@@ -202,12 +207,82 @@ __global__ void __launch_bounds__(256) k_predecode(PredecodeArgs a)
                 store_pair(row, p0, p1);
                 store_pair(row + 2, p0, p1);
             } else {                              // pitch 3: texel 0 three times
-                row[0] = p0;
-                row[1] = p0;
-                row[2] = p0;
+                global_texel *g = (global_texel *)row;
+                const u32x2_t v = {p0.x, p0.y};
+                g[0] = v;
+                g[1] = v;
+                g[2] = v;
             }
         }
     }
+}
+
+// The unpack segment of (pyramid or interleaved slot set, level) of a single
+// material's plan entry `seg`.
+__device__ __forceinline__ UnpackSeg material_seg(const PredecodeArgs &a, uint32_t seg)
+{
+    const uint32_t l = a.p.seg_lvl[seg];
+    const uint32_t il = a.m.interleaved;
+    UnpackSeg sg;
+    for (uint32_t t = 0; t < (uint32_t)kMaxTextures; ++t) {
+        const TexDesc &T = a.m.tex[il ? (t < a.m.n_tex ? t : 0u) : a.p.seg_tex[seg]];
+        sg.blocks[t] = T.blocks + T.blk_off[l];
+    }
+    const TexDesc &T0 = a.m.tex[il ? 0u : a.p.seg_tex[seg]];
+    sg.lw = max(T0.w >> l, 1u);
+    sg.lh = max(T0.h >> l, 1u);
+    sg.texels = a.texels + (il ? (size_t)kMaxTextures : 1u) * T0.tex_off[l];
+    sg.wg0 = a.p.seg_wg[seg];
+    sg.flags = il ? kSegInterleaved : 0u;
+    return sg;
+}
+
+template <bool SIGNED>
+__global__ void __launch_bounds__(256) k_predecode(PredecodeArgs a)
+{
+    __shared__ uint32_t table[kTableWords];
+    // each lane's block palette, entry-major so that lane L's entries sit in
+    // consecutive 8-byte slots across lanes, and its 16 four-bit slots
+    __shared__ uint2 palette[16][256];
+    __shared__ uint2 slots[256];
+    load_table(table);
+    // segment of this workgroup (uniform scan over at most 64 entries)
+    const uint32_t wg = blockIdx.x;
+    uint32_t seg = 0;
+    while (seg + 1 < a.p.n_seg && a.p.seg_wg[seg + 1] <= wg) ++seg;
+    const UnpackSeg sg = material_seg(a, seg);
+    unpack_chunk<SIGNED>(sg, wg - sg.wg0, table, palette, slots);
+}
+
+// Every material of a batch in one launch: workgroup c unpacks chunk c of
+// the segment table (and c + gridDim.x, ... when the table holds more chunks
+// than one grid), its segment read from the chunk map (two dependent scalar
+// loads; a search over the table costs a load per step, on every
+// workgroup). One chunk per workgroup lets the hardware start a workgroup as
+// soon as another retires, which keeps the stores of one chunk in flight
+// beside the loads of the next (a persistent loop serialises them).
+__global__ void __launch_bounds__(256) k_predecode_batch(const UnpackSeg *segs, const uint32_t *chunk_seg,
+                                                         uint32_t n_chunks)
+{
+    __shared__ uint32_t table[kTableWords];
+    __shared__ uint2 palette[16][256];
+    __shared__ uint2 slots[256];
+    load_table(table);
+    for (uint32_t c = blockIdx.x; c < n_chunks; c += gridDim.x) {
+        const UnpackSeg sg = segs[chunk_seg[c]];
+        if (sg.flags & kSegSigned) unpack_chunk<true>(sg, c - sg.wg0, table, palette, slots);
+        else unpack_chunk<false>(sg, c - sg.wg0, table, palette, slots);
+        __syncthreads();                          // palette and slots are reused by the next chunk
+    }
+}
+
+hipError_t launch_predecode_batch(const UnpackSeg *segs, const uint32_t *chunk_seg, uint32_t n_chunks, hipStream_t s)
+{
+    if (n_chunks == 0) return hipSuccess;
+    // a grid of at most 2^22 workgroups (2^30 threads); larger tables loop
+    const unsigned grid = std::min<unsigned>(n_chunks, 1u << 22);
+    k_predecode_batch<<<grid, 256, 0, s>>>(segs, chunk_seg, n_chunks);
+    return hipGetLastError();
 }
 
 hipError_t launch_predecode(const MaterialDesc &m, const PredecodePlan &p, uint2 *texels, hipStream_t s)
@@ -517,8 +592,18 @@ __global__ void k_batch_items(BatchArgs a)
 }
 
 hipError_t write_batch_table(const MaterialDesc *mats, const BatchSlot *slots, uint32_t n_mats, uint32_t out_dim,
-                             const WsHeader &header, void *ws, size_t table_off, hipStream_t s)
+                             const WsHeader &header, void *ws, size_t table_off, const UnpackSeg *segs,
+                             uint32_t n_seg, size_t segs_off, const uint32_t *chunk_seg, uint32_t n_chunks,
+                             size_t chunk_seg_off, hipStream_t s)
 {
+    if (n_seg) {
+        hipError_t e = hipMemcpyAsync(static_cast<uint8_t *>(ws) + segs_off, segs, sizeof(UnpackSeg) * n_seg,
+                                      hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return e;
+        e = hipMemcpyAsync(static_cast<uint8_t *>(ws) + chunk_seg_off, chunk_seg, sizeof(uint32_t) * n_chunks,
+                           hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return e;
+    }
     // the header at byte 0, then (from table_off) the material table: one copy
     std::vector<uint8_t> host(table_off + sizeof(BatchMat) * n_mats, 0);
     std::memcpy(host.data(), &header, sizeof header);
@@ -542,12 +627,12 @@ hipError_t write_batch_table(const MaterialDesc *mats, const BatchSlot *slots, u
     }
     hipError_t e = hipMemcpyAsync(ws, host.data(), host.size(), hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return e;
-    return hipStreamSynchronize(s);           // the host table goes out of scope
+    return hipStreamSynchronize(s);           // the host tables go out of scope
 }
 
 hipError_t launch_batch(void *ws, size_t table_off, size_t items_off, const WsLayout &rel, const MlpShape &sh,
                         MlpKind kind, const float *queries, const uint32_t *offsets, uint32_t n_mats,
-                        uint32_t n_total, float *out, unsigned workgroups, uint32_t interleave, hipStream_t s)
+                        uint32_t n_total, float *out, const BatchShape &shape, hipStream_t s)
 {
     BatchArgs a;
     std::memset(&a, 0, sizeof a);
@@ -561,14 +646,17 @@ hipError_t launch_batch(void *ws, size_t table_off, size_t items_off, const WsLa
     a.n_mats = n_mats;
     a.n_total = n_total;
     a.out_dim = sh.out;
-    a.interleave = interleave;
+    a.interleave = shape.interleave;
+    a.run = shape.run;
     k_batch_items<<<1, 64, 0, s>>>(a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const unsigned grid = std::max(kXcds, (std::min(workgroups, 256u * 16u) + kXcds - 1) / kXcds * kXcds);
+    const uint32_t waves = shape.waves == 2 ? 2u : 4u;
+    const unsigned cap = 256u * 64u / waves;               // at most 64 waves per CU's worth
+    const unsigned grid = std::max(kXcds, (std::min(shape.workgroups, cap) + kXcds - 1) / kXcds * kXcds);
     switch (kind) {
-    case MLP_MFMA_F16: return launch_batch_f16(a, sh, grid, s);
-    case MLP_VALU_F32: return launch_batch_f32(a, sh, grid, s);
+    case MLP_MFMA_F16: return launch_batch_f16(a, sh, grid, waves, s);
+    case MLP_VALU_F32: return launch_batch_f32(a, sh, grid, waves, s);
     default: return hipErrorInvalidValue;
     }
 }

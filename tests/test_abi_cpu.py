@@ -34,7 +34,7 @@ def test_every_declared_symbol_is_exported(bcf):
 
 
 def test_abi_version(bcf):
-    assert bcf.abi_version() == 1
+    assert bcf.abi_version() == 2
 
 
 def test_texture_bytes_matches_oracle_and_rejects_bad_sizes(bcf):
@@ -237,6 +237,13 @@ def test_batch_validation(bcf):
                                     C.c_void_p(FAKE), None, None) == 1
     assert bcf.lib.bcf_prepare_batch(arr, 2, 1, C.c_void_p(FAKE), 100, None) == 1
     assert "workspace" in bcf.lib.bcf_last_error().decode()
+    # launch shapes outside what the kernels take
+    from paper_2311_16121_amd._lib import _BatchPlan
+    for plan, msg in (((0, 1, 1, 3), "waves"), ((0, 1, 65, 4), "run")):
+        p = _BatchPlan(*plan)
+        assert bcf.lib.bcf_decode_batch(arr, 2, 1, C.c_void_p(FAKE), C.c_void_p(FAKE), C.c_void_p(FAKE), 10,
+                                        C.c_void_p(FAKE), C.byref(p), None) == 1
+        assert msg in bcf.lib.bcf_last_error().decode()
 
 
 def test_workspace_not_filled_by_prepare_is_rejected(bcf):

@@ -151,12 +151,15 @@ def test_batch_plans_agree_and_tuner_returns_one(bcf, shared_only):
     batch.unpack()
     q_all, offs = dev(np.concatenate(qs)), dev(offsets)
     ref = batch.decode(q_all, offs).cpu().numpy()
-    for plan in ((8, 0), (8, 1), (256, 0), (4096, 1), (1000, 0)):
+    for plan in ((8, 0), (8, 1), (256, 0), (4096, 1), (1000, 0), (8, 1, 4, 2), (512, 1, 2, 2), (64, 0, 1, 2),
+                 (3000, 1, 64, 4), (16, 1, 3, 4)):
         got = batch.decode(q_all, offs, plan=plan).cpu().numpy()
         assert np.array_equal(got.view(np.uint32), ref.view(np.uint32)), plan
     plan, ms = batch.tune(q_all, offs)
     log(f"tuned plan {plan}: {ms:.4f} ms")
-    assert plan[0] in (256, 512, 1024, 2048, 4096) and plan[1] in (0, 1) and ms > 0
+    workgroups, interleave, run, waves = plan
+    assert waves in (2, 4) and workgroups * waves in (1024, 2048, 4096, 8192, 16384) and ms > 0
+    assert (interleave, run) in ((0, 1), (1, 1), (1, 2), (1, 4))
     got = batch.decode(q_all, offs, plan=plan).cpu().numpy()
     assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
 
