@@ -25,9 +25,10 @@ namespace {
 
 constexpr float kA = 31.0f / 64.0f;      // a of eq. (6) for the unsigned format
 constexpr int kTrainThreads = 256;
-// the backward runs two waves per workgroup: its LDS (per-wave reduction
-// buffers plus the privatised small levels) then fits three workgroups per CU
-constexpr int kBwdThreads = 128;
+// the backward runs three waves per workgroup: its LDS (per-wave reduction
+// buffers, the privatised small levels, the MLP and the level table, ≈ 77 KB)
+// then fits two workgroups per CU
+constexpr int kBwdThreads = 192;
 constexpr int kBwdWaves = kBwdThreads / 64;
 
 __global__ void __launch_bounds__(256) k_train_zero(float *p, uint32_t n)
@@ -204,14 +205,33 @@ __global__ void __launch_bounds__(kTrainThreads) k_train_blocks(TrainDesc d)
 // ---------------------------------------------------------------------------
 // queries
 
+// Per pyramid and level, for the query kernels' LDS: x = level width,
+// y = level height, z = first texel of the level in the images. A level picked
+// per query indexes it; indexing the descriptor's arrays instead makes the
+// compiler hold every level's values in registers across the query loop.
+typedef uint4 TrainLevelLut[kMaxTextures][kMaxLevels];
+
+// Every thread of the workgroup takes part; the caller synchronises.
+__device__ __forceinline__ void load_level_lut(const TrainDesc &d, TrainLevelLut &lut)
+{
+    for (uint32_t e = threadIdx.x; e < (uint32_t)(kMaxTextures * kMaxLevels); e += blockDim.x) {
+        const uint32_t ti = e / kMaxLevels, l = e % kMaxLevels;
+        const TrainTexDesc &tx = d.tex[ti < d.n_tex ? ti : 0u];
+        lut[ti][l] = l < tx.levels ? make_uint4(max(tx.w >> l, 1u), max(tx.h >> l, 1u), tx.tex_off[l], 0u)
+                                   : make_uint4(1u, 1u, 0u, 0u);
+    }
+}
+
 // The 32 taps of a query (4 pyramids x 2 levels x 4 texels): texel index and
 // weight (bilinear times trilinear); pyramids past n_tex get weight 0.
-__device__ __forceinline__ void taps(const TrainDesc &d, float u, float v, float s, uint32_t idx[32], float wt[32])
+__device__ __forceinline__ void taps(const TrainDesc &d, const TrainLevelLut &lut, float u, float v, float s,
+                                     uint32_t idx[32], float wt[32])
 {
     const float uf = u - floorf(u), vf = v - floorf(v);          // wrap addressing
 #pragma unroll
     for (int ti = 0; ti < kMaxTextures; ++ti) {
         const TrainTexDesc &tx = d.tex[ti < (int)d.n_tex ? ti : 0];
+        const uint32_t slot = ti < (int)d.n_tex ? (uint32_t)ti : 0u;
         const float si = fminf(fmaxf(s + tx.bias, 0.0f), (float)(tx.levels - 1));   // NaN -> 0
         const uint32_t l0 = (uint32_t)floorf(si);
         const uint32_t l1 = min(l0 + 1u, tx.levels - 1u);
@@ -221,13 +241,14 @@ __device__ __forceinline__ void taps(const TrainDesc &d, float u, float v, float
         for (int k = 0; k < 2; ++k) {
             const uint32_t l = k ? l1 : l0;
             const float lw = on * (k ? lam : 1.0f - lam);
-            const uint32_t wl = max(tx.w >> l, 1u), hl = max(tx.h >> l, 1u);
+            const uint4 e = lut[slot][l];
+            const uint32_t wl = e.x, hl = e.y;
             const float x = fmaf(uf, (float)wl, -0.5f), y = fmaf(vf, (float)hl, -0.5f);
             const float x0 = floorf(x), y0 = floorf(y);
             const float fx = x - x0, fy = y - y0;
             const uint32_t xa = (uint32_t)(int)x0 & (wl - 1u), xb = (xa + 1u) & (wl - 1u);
             const uint32_t ya = (uint32_t)(int)y0 & (hl - 1u), yb = (ya + 1u) & (hl - 1u);
-            const uint32_t base = tx.tex_off[l];
+            const uint32_t base = e.z;
             const int o = 8 * ti + 4 * k;
             idx[o + 0] = base + ya * wl + xa;
             idx[o + 1] = base + ya * wl + xb;
@@ -241,11 +262,12 @@ __device__ __forceinline__ void taps(const TrainDesc &d, float u, float v, float
     }
 }
 
-__device__ __forceinline__ void features(const TrainDesc &d, float u, float v, float s, float z[12])
+__device__ __forceinline__ void features(const TrainDesc &d, const TrainLevelLut &lut, float u, float v, float s,
+                                         float z[12])
 {
     uint32_t idx[32];
     float wt[32];
-    taps(d, u, v, s, idx, wt);
+    taps(d, lut, u, v, s, idx, wt);
 #pragma unroll
     for (int i = 0; i < 12; ++i) z[i] = 0.0f;
 #pragma unroll
@@ -258,40 +280,107 @@ __device__ __forceinline__ void features(const TrainDesc &d, float u, float v, f
     }
 }
 
-typedef const __attribute__((address_space(4))) float const_float;
+// The MLP's parameters in LDS, one padded row per neuron: its weights, its
+// bias, zeros (layer 0's inputs padded to 12, the output layer to kMaxOut
+// rows). Every lane reads the same address, so a read is a broadcast; rows
+// are read as 16-byte vectors through a pointer that passes an empty asm per
+// row, so that the optimiser neither hoists the reads out of the query loop
+// nor keeps more than a row of weights live (held in registers instead, the
+// unrolled layers' weights would be spilled).
+template <int H, int NH>
+struct __align__(16) MlpLds {
+    float w0[H][16];                          // inputs 0..11, bias at 12
+    float wh[NH > 1 ? NH - 1 : 1][H][H + 4];  // inputs 0..H-1, bias at H
+    float wl[kMaxOut][H + 4];
+};
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) const f32x4 lds_f32x4;
+
+// Row `row` (N_IN weights then the bias) into registers: w[0..N_IN) weights,
+// w[N_IN] bias. The read is ordered after `after` is computed (the previous
+// row's result), so that the scheduler cannot issue every row's reads at once.
+template <int N_IN>
+__device__ __forceinline__ void lds_row(const float *row, float after, float (&w)[N_IN + 1])
+{
+    uint32_t a = (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) float *)row;
+    asm volatile("" : "+v"(a) : "v"(after));
+    const lds_f32x4 *r = (const lds_f32x4 *)(uintptr_t)a;
+#pragma unroll
+    for (int k = 0; k < (N_IN + 4) / 4; ++k) {
+        const f32x4 v = r[k];
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if (4 * k + e <= N_IN) w[4 * k + e] = v[e];
+    }
+}
+
+// Marks v[0..N) as rewritten, N a multiple of 4: every update of them before
+// this point is complete, and (the asm being volatile) no later lds_row reads
+// move above it. Keeps a row-by-row update of a vector row by row.
+template <int N>
+__device__ __forceinline__ void pin(float (&v)[N])
+{
+#pragma unroll
+    for (int k = 0; k < N; k += 4) asm volatile("" : "+v"(v[k]), "+v"(v[k + 1]), "+v"(v[k + 2]), "+v"(v[k + 3]));
+}
+
+// Every thread of the workgroup takes part; synchronises the workgroup.
+template <int H, int NH>
+__device__ __forceinline__ void load_mlp(const TrainDesc &d, MlpLds<H, NH> &m)
+{
+    const uint32_t n0 = d.dims[0], c = d.dims[NH + 1];
+    const float *P = d.params;
+    for (uint32_t e = threadIdx.x; e < (uint32_t)(H * 16); e += blockDim.x) {
+        const uint32_t j = e / 16u, i = e % 16u;
+        m.w0[j][i] = i < n0 ? P[d.w_off[0] + j * n0 + i] : (i == 12 ? P[d.b_off[0] + j] : 0.0f);
+    }
+    for (uint32_t e = threadIdx.x; e < (uint32_t)((NH - 1) * H * (H + 4)); e += blockDim.x) {
+        const uint32_t l = e / (H * (H + 4)), r = e % (H * (H + 4)), j = r / (H + 4), i = r % (H + 4);
+        m.wh[l][j][i] = i < H ? P[d.w_off[l + 1] + j * H + i] : (i == H ? P[d.b_off[l + 1] + j] : 0.0f);
+    }
+    for (uint32_t e = threadIdx.x; e < (uint32_t)(kMaxOut * (H + 4)); e += blockDim.x) {
+        const uint32_t j = e / (H + 4), i = e % (H + 4);
+        m.wl[j][i] = j >= c ? 0.0f : i < H ? P[d.w_off[NH] + j * H + i] : (i == H ? P[d.b_off[NH] + j] : 0.0f);
+    }
+    __syncthreads();
+}
 
 // Forward MLP with the hidden activations kept (act[l] = output of hidden layer l).
 template <int H, int NH>
-__device__ __forceinline__ void mlp_forward(const TrainDesc &d, const float z[12], float act[NH][H],
+__device__ __forceinline__ void mlp_forward(const MlpLds<H, NH> &m, uint32_t c, const float z[12], float act[NH][H],
                                             float out[kMaxOut])
 {
-    const_float *P = (const_float *)d.params;
-    const uint32_t n0 = d.dims[0];
+    // inputs past dims[0] are zero (their weights are zero too)
 #pragma unroll
     for (int j = 0; j < H; ++j) {
-        float acc = P[d.b_off[0] + j];
+        float w[13];
+        lds_row<12>(m.w0[j], j ? act[0][j - 1] : z[0], w);
+        float acc = w[12];
 #pragma unroll
-        for (int i = 0; i < 12; ++i)
-            if ((uint32_t)i < n0) acc = fmaf(P[d.w_off[0] + j * n0 + i], z[i], acc);
+        for (int i = 0; i < 12; ++i) acc = fmaf(w[i], z[i], acc);
         act[0][j] = fmaxf(acc, 0.0f);
     }
 #pragma unroll
     for (int l = 1; l < NH; ++l)
 #pragma unroll
         for (int j = 0; j < H; ++j) {
-            float acc = P[d.b_off[l] + j];
+            float w[H + 1];
+            lds_row<H>(m.wh[l - 1][j], j ? act[l][j - 1] : act[l - 1][H - 1], w);
+            float acc = w[H];
 #pragma unroll
-            for (int i = 0; i < H; ++i) acc = fmaf(P[d.w_off[l] + j * H + i], act[l - 1][i], acc);
+            for (int i = 0; i < H; ++i) acc = fmaf(w[i], act[l - 1][i], acc);
             act[l][j] = fmaxf(acc, 0.0f);
         }
-    const uint32_t c = d.dims[NH + 1];
 #pragma unroll
     for (int j = 0; j < kMaxOut; ++j) {
         float acc = 0.0f;
         if ((uint32_t)j < c) {
-            acc = P[d.b_off[NH] + j];
+            float w[H + 1];
+            lds_row<H>(m.wl[j], j ? out[j - 1] : act[NH - 1][H - 1], w);
+            acc = w[H];
 #pragma unroll
-            for (int i = 0; i < H; ++i) acc = fmaf(P[d.w_off[NH] + j * H + i], act[NH - 1][i], acc);
+            for (int i = 0; i < H; ++i) acc = fmaf(w[i], act[NH - 1][i], acc);
         }
         out[j] = acc;
     }
@@ -301,11 +390,15 @@ template <int H, int NH>
 __global__ void __launch_bounds__(kTrainThreads) k_train_forward(TrainDesc d, const float *queries, uint32_t n,
                                                                  float *out)
 {
+    __shared__ MlpLds<H, NH> mlp;
+    __shared__ TrainLevelLut lut;
+    load_level_lut(d, lut);
+    load_mlp<H, NH>(d, mlp);                  // synchronises, also for `lut`
     const uint32_t c = d.dims[NH + 1];
     for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
         float z[12], act[NH][H], o[kMaxOut];
-        features(d, queries[3u * q], queries[3u * q + 1u], queries[3u * q + 2u], z);
-        mlp_forward<H, NH>(d, z, act, o);
+        features(d, lut, queries[3u * q], queries[3u * q + 1u], queries[3u * q + 2u], z);
+        mlp_forward<H, NH>(mlp, c, z, act, o);
 #pragma unroll
         for (int j = 0; j < kMaxOut; ++j)
             if ((uint32_t)j < c) out[(size_t)q * c + j] = o[j];
@@ -360,12 +453,14 @@ __global__ void __launch_bounds__(kBwdThreads, 2) k_train_backward(TrainDesc d, 
     // every query that reaches them hits the same few texels, so they are
     // summed in LDS per workgroup and added to memory once at the end.
     __shared__ float small[kMaxTextures * kTrainSmallTexels * 3];
+    __shared__ MlpLds<H, NH> mlp;
+    __shared__ TrainLevelLut lut;
     for (uint32_t i = threadIdx.x; i < kMaxTextures * kTrainSmallTexels * 3; i += kBwdThreads) small[i] = 0.0f;
-    __syncthreads();
+    load_level_lut(d, lut);
+    load_mlp<H, NH>(d, mlp);                  // synchronises, also for `small` and `lut`
 
     const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
     const uint32_t n0 = d.dims[0], c = d.dims[NH + 1];
-    const_float *P = (const_float *)d.params;
     float acc0[K0], accH[NH > 1 ? NH - 1 : 1][KH], accL[KL];
 #pragma unroll
     for (int k = 0; k < K0; ++k) acc0[k] = 0.0f;
@@ -386,8 +481,8 @@ __global__ void __launch_bounds__(kBwdThreads, 2) k_train_backward(TrainDesc d, 
         const float v = live ? queries[3u * q + 1u] : 0.0f;
         const float s = live ? queries[3u * q + 2u] : 0.0f;
         float z[12], act[NH][H], o[kMaxOut];
-        features(d, u, v, s, z);
-        mlp_forward<H, NH>(d, z, act, o);
+        features(d, lut, u, v, s, z);
+        mlp_forward<H, NH>(mlp, c, z, act, o);
         float delta[kTrainMaxHidden];
 #pragma unroll
         for (int j = 0; j < kTrainMaxHidden; ++j)
@@ -405,17 +500,34 @@ __global__ void __launch_bounds__(kBwdThreads, 2) k_train_backward(TrainDesc d, 
         // back through the hidden layers: delta of hidden layer l's pre-activation
 #pragma unroll
         for (int l = NH - 1; l >= 0; --l) {
-            const uint32_t rows = l == NH - 1 ? c : H;           // outputs of layer l + 1
-            const uint32_t wo = d.w_off[l + 1], stride = H;
+            // g = W_{l+1}^T delta, summed over the rows j in order; the rows
+            // of W_{l+1} are read whole (the output layer's past c are zero,
+            // and so are the deltas there)
             float g[H];
 #pragma unroll
-            for (int i = 0; i < H; ++i) {
-                float acc = 0.0f;
+            for (int i = 0; i < H; ++i) g[i] = 0.0f;
+            if (l == NH - 1) {
 #pragma unroll
-                for (int j = 0; j < (l == NH - 1 ? kMaxOut : H); ++j)
-                    if ((uint32_t)j < rows) acc = fmaf(P[wo + j * stride + i], delta[j], acc);
-                g[i] = act[l][i] > 0.0f ? acc : 0.0f;
+                for (int j = 0; j < kMaxOut; ++j)
+                    if ((uint32_t)j < c) {
+                        float w[H + 1];
+                        lds_row<H>(mlp.wl[j], g[H - 1], w);
+#pragma unroll
+                        for (int i = 0; i < H; ++i) g[i] = fmaf(w[i], delta[j], g[i]);
+                        pin(g);
+                    }
+            } else {
+#pragma unroll
+                for (int j = 0; j < H; ++j) {
+                    float w[H + 1];
+                    lds_row<H>(mlp.wh[l][j], g[H - 1], w);
+#pragma unroll
+                    for (int i = 0; i < H; ++i) g[i] = fmaf(w[i], delta[j], g[i]);
+                    pin(g);
+                }
             }
+#pragma unroll
+            for (int i = 0; i < H; ++i) g[i] = act[l][i] > 0.0f ? g[i] : 0.0f;
 #pragma unroll
             for (int i = 0; i < H; ++i) delta[i] = g[i];
             // parameters of layer l: inputs are act[l - 1] (or z), outputs delta
@@ -438,17 +550,19 @@ __global__ void __launch_bounds__(kBwdThreads, 2) k_train_backward(TrainDesc d, 
         // dL/dz = W_0^T delta, then onto the 32 taps
         float dz[12];
 #pragma unroll
-        for (int i = 0; i < 12; ++i) {
-            float acc = 0.0f;
-            if ((uint32_t)i < n0)
+        for (int i = 0; i < 12; ++i) dz[i] = 0.0f;
 #pragma unroll
-                for (int j = 0; j < H; ++j) acc = fmaf(P[d.w_off[0] + j * n0 + i], delta[j], acc);
-            dz[i] = acc;
+        for (int j = 0; j < H; ++j) {
+            float w[13];
+            lds_row<12>(mlp.w0[j], dz[11], w);
+#pragma unroll
+            for (int i = 0; i < 12; ++i) dz[i] = fmaf(w[i], delta[j], dz[i]);
+            pin(dz);
         }
         if (live) {
             uint32_t idx[32];
             float wt[32];
-            taps(d, u, v, s, idx, wt);
+            taps(d, lut, u, v, s, idx, wt);
 #pragma unroll
             for (int k = 0; k < 32; ++k) {
                 const int t = k / 8;
