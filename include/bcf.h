@@ -246,6 +246,24 @@ bcf_status bcf_prepare_batch(const bcf_material *mats, uint32_t n_mats, bcf_prec
  * all four from one span; results do not depend on the layout. */
 bcf_status bcf_unpack_batch(const bcf_material *mats, uint32_t n_mats, void *ws, void *stream);
 
+/* bcf_unpack_batch restricted to the blocks that these queries' trilinear
+ * footprints read (eqs. 9 and 10 at the queries' LODs), the way Section 5.2's
+ * renderer decodes only the blocks its samples touch: a bcf_decode_batch
+ * with the same queries and offsets, and no call in between that writes the
+ * workspace, then returns exactly what it returns after bcf_unpack_batch.
+ * Texels of other blocks keep whatever the workspace held, so a decode of
+ * other queries needs its own unpack. queries, offsets and n_total as for
+ * bcf_decode_batch (device memory; offsets read on the device). For the
+ * position-interleaved materials the footprints' block positions are first
+ * marked in a byte table of the workspace (three launches: clear, item
+ * prefix, mark), then one launch unpacks the marked positions and every
+ * block of the other materials. Asynchronous, no allocation or host
+ * synchronisation: it can be captured in a graph with bcf_decode_batch.
+ * Errors as for bcf_unpack_batch, and BCF_ERR_INVALID_ARG for NULL or
+ * misaligned queries (n_total > 0) or offsets. */
+bcf_status bcf_unpack_batch_touched(const bcf_material *mats, uint32_t n_mats, void *ws, const float *queries,
+                                    const uint32_t *offsets, uint32_t n_total, void *stream);
+
 /* Decodes every material's queries in one persistent launch (after a small
  * launch that turns offsets into work items). Asynchronous and free of host
  * synchronisation and allocation, so it can be captured in a graph together

@@ -82,6 +82,9 @@ def _load():
     L.bcf_prepare_batch.argtypes = [C.POINTER(_Material), C.c_uint32, C.c_int, C.c_void_p, C.c_size_t, C.c_void_p]
     L.bcf_unpack_batch.restype = C.c_int
     L.bcf_unpack_batch.argtypes = [C.POINTER(_Material), C.c_uint32, C.c_void_p, C.c_void_p]
+    L.bcf_unpack_batch_touched.restype = C.c_int
+    L.bcf_unpack_batch_touched.argtypes = [C.POINTER(_Material), C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                           C.c_uint32, C.c_void_p]
     L.bcf_decode_batch.restype = C.c_int
     L.bcf_decode_batch.argtypes = [C.POINTER(_Material), C.c_uint32, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
                                    C.c_uint32, C.c_void_p, C.POINTER(_BatchPlan), C.c_void_p]
@@ -112,7 +115,8 @@ lib = _load()
 EXPORTED = ("bcf_abi_version", "bcf_last_error", "bcf_texture_bytes", "bcf_prepare",
             "bcf_decode", "bcf_unpack", "bcf_decode_unpacked", "bcf_calibrate", "bcf_decode_blocks",
             "bcf_decode_noalloc",
-            "bcf_batch_workspace_size", "bcf_prepare_batch", "bcf_unpack_batch", "bcf_decode_batch",
+            "bcf_batch_workspace_size", "bcf_prepare_batch", "bcf_unpack_batch", "bcf_unpack_batch_touched",
+            "bcf_decode_batch",
             "bcf_tune_batch", "bcf_train_workspace_size", "bcf_train_forward", "bcf_train_backward")
 
 
@@ -302,7 +306,9 @@ class Batch:
     materials: list of Material (one MLP shape); precision FP16 or FP32.
     """
 
-    def __init__(self, materials, precision=Precision.FP16, stream=None):
+    def __init__(self, materials, precision=Precision.FP16, stream=None, ws_fill=None):
+        """ws_fill: a byte written over the whole workspace before it is
+        prepared (lets a test see which texels an unpack wrote)."""
         import torch
         self.materials = list(materials)
         self.precision = Precision(precision)
@@ -312,6 +318,8 @@ class Batch:
         _check(lib.bcf_batch_workspace_size(self.c, n, int(self.precision), C.byref(nbytes)),
                "bcf_batch_workspace_size")
         ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.materials[0].params.device)
+        if ws_fill is not None:
+            ws.fill_(int(ws_fill))
         off = (-ws.data_ptr()) % 256
         self.ws = ws[off: off + nbytes.value]
         _check(lib.bcf_prepare_batch(self.c, n, int(self.precision), C.c_void_p(self.ws.data_ptr()),
@@ -324,6 +332,15 @@ class Batch:
     def unpack(self, stream=None):
         _check(lib.bcf_unpack_batch(self.c, len(self), C.c_void_p(self.ws.data_ptr()), _stream(stream)),
                "bcf_unpack_batch")
+
+    def unpack_touched(self, queries, offsets, stream=None):
+        """Unpacks only the blocks these queries read (then decode() with the
+        same queries and offsets)."""
+        q = _queries(queries)
+        offs = self._offsets(offsets)
+        _check(lib.bcf_unpack_batch_touched(self.c, len(self), C.c_void_p(self.ws.data_ptr()),
+                                            C.c_void_p(q.data_ptr()), C.c_void_p(offs.data_ptr()), q.shape[0],
+                                            _stream(stream)), "bcf_unpack_batch_touched")
 
     @staticmethod
     def _offsets(offsets):

@@ -447,8 +447,9 @@ bcf_status bind_train_ws(bcf::TrainDesc *d, void *ws)
 // header, the material table, the item prefix, the unpack segment table and
 // its chunk map, then per material its texel scratch, then the MLP operands.
 struct BatchLayout {
-    size_t table_off, items_off, segs_off, chunk_seg_off, total;
+    size_t table_off, items_off, segs_off, chunk_seg_off, marks_off, units_off, total;
     uint32_t n_seg, n_chunks;               // unpack segments of every material, their chunks of 256 lanes
+    uint32_t n_units;                       // work units of the touched-blocks unpack
     std::vector<bcf::BatchSlot> slots;
     std::vector<bcf::MaterialDesc> descs;
     bcf::MlpShape sh;
@@ -475,6 +476,7 @@ bcf_status describe_batch(const bcf_material *mats, uint32_t n_mats, bcf_precisi
     b->segs_off = off;                      // its size is known once the materials are described
     b->n_seg = 0;
     b->n_chunks = 0;
+    b->n_units = 0;
     for (uint32_t k = 0; k < n_mats; ++k) {
         bcf::MlpShape sh;
         const bcf_status st = describe(&mats[k], &b->descs[k], &sh);
@@ -492,10 +494,18 @@ bcf_status describe_batch(const bcf_material *mats, uint32_t n_mats, bcf_precisi
         const bcf::PredecodePlan plan = predecode_plan(b->descs[k]);
         b->n_seg += plan.n_seg;
         b->n_chunks += plan.seg_wg[plan.n_seg];
+        for (uint32_t j = 0; j < plan.n_seg; ++j) {
+            const uint32_t chunks = plan.seg_wg[j + 1] - plan.seg_wg[j];
+            b->n_units += b->descs[k].interleaved ? (chunks + 3) / 4 : chunks;
+        }
     }
     off = align_up(off + sizeof(bcf::UnpackSeg) * b->n_seg, 256);
     b->chunk_seg_off = off;                 // segment of each unpack chunk
     off = align_up(off + sizeof(uint32_t) * b->n_chunks, 256);
+    b->marks_off = off;                     // one byte per block position of every chunk
+    off = align_up(off + (size_t)64 * b->n_chunks, 256);
+    b->units_off = off;                     // first chunk of each touched-unpack unit
+    off = align_up(off + sizeof(uint32_t) * b->n_units, 256);
     for (uint32_t k = 0; k < n_mats; ++k) {
         b->slots[k].scratch_off = off;
         b->slots[k].scratch_bytes = scratch_texels(b->descs[k]) * 8;
@@ -758,8 +768,9 @@ bcf_status bcf_prepare_batch(const bcf_material *mats, uint32_t n_mats, bcf_prec
     }
     // the unpack segments of every material, numbered in one sequence of chunks
     std::vector<bcf::UnpackSeg> segs;
-    std::vector<uint32_t> chunk_seg(b.n_chunks);
+    std::vector<uint32_t> chunk_seg(b.n_chunks), units;
     segs.reserve(b.n_seg);
+    units.reserve(b.n_units);
     uint32_t chunk0 = 0;
     for (uint32_t k = 0; k < n_mats; ++k) {
         const bcf::MaterialDesc &d = b.descs[k];
@@ -779,11 +790,20 @@ bcf_status bcf_prepare_batch(const bcf_material *mats, uint32_t n_mats, bcf_prec
             g.lh = level_dim(T0.h, l);
             g.wg0 = chunk0 + plan.seg_wg[j];
             g.flags = (d.interleaved ? bcf::kSegInterleaved : 0u) | (d.is_signed ? bcf::kSegSigned : 0u);
-            std::fill(chunk_seg.begin() + g.wg0, chunk_seg.begin() + chunk0 + plan.seg_wg[j + 1],
-                      (uint32_t)segs.size());
+            const uint32_t end = chunk0 + plan.seg_wg[j + 1];
+            std::fill(chunk_seg.begin() + g.wg0, chunk_seg.begin() + end, (uint32_t)segs.size());
+            for (uint32_t c = g.wg0; c < end; c += d.interleaved ? 4u : 1u) units.push_back(c);
+            if (d.interleaved) b.slots[k].seg_chunk[l] = g.wg0;
             segs.push_back(g);
         }
         chunk0 += plan.seg_wg[plan.n_seg];
+    }
+    if (!units.empty()) {
+        // write_batch_table below synchronises the stream before `units` goes
+        st = device_status(hipMemcpyAsync(static_cast<uint8_t *>(ws) + b.units_off, units.data(),
+                                          sizeof(uint32_t) * units.size(), hipMemcpyHostToDevice, s),
+                           "unit table copy");
+        if (st != BCF_OK) return st;
     }
     const uint64_t hash = batch_hash(mats, n_mats, p);
     st = device_status(bcf::write_batch_table(b.descs.data(), b.slots.data(), n_mats, b.sh.out,
@@ -833,6 +853,33 @@ unsigned default_workgroups(uint32_t n_total)
 }
 
 }  // namespace
+
+bcf_status bcf_unpack_batch_touched(const bcf_material *mats, uint32_t n_mats, void *ws, const float *queries,
+                                    const uint32_t *offsets, uint32_t n_total, void *stream)
+{
+    BatchLayout b;
+    bcf_status st = describe_batch(mats, n_mats, BCF_FP16, &b);
+    if (st != BCF_OK) return st;
+    if (!ws || !aligned(ws, 256)) return fail(BCF_ERR_INVALID_ARG, "workspace NULL or not 256-byte aligned");
+    if (!offsets || !aligned(offsets, 4)) return fail(BCF_ERR_INVALID_ARG, "offsets NULL or misaligned");
+    if (n_total > 0 && (!queries || !aligned(queries, 4)))
+        return fail(BCF_ERR_INVALID_ARG, "queries NULL or misaligned");
+    // either batch precision: the tables and the scratch layout are the same (and so is the hash)
+    if ((st = check_ws(ws, -1, n_mats, batch_hash(mats, n_mats, BCF_FP16), "bcf_prepare_batch")) != BCF_OK)
+        return st;
+    uint8_t *base = static_cast<uint8_t *>(ws);
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    st = device_status(bcf::launch_batch_mark(ws, b.table_off, b.items_off, queries, offsets, n_mats, n_total,
+                                              base + b.marks_off, (size_t)64 * b.n_chunks, s),
+                       "mark launch");
+    if (st != BCF_OK) return st;
+    return device_status(bcf::launch_predecode_touched(reinterpret_cast<const bcf::UnpackSeg *>(base + b.segs_off),
+                                                       reinterpret_cast<const uint32_t *>(base + b.chunk_seg_off),
+                                                       b.n_seg, b.n_chunks,
+                                                       reinterpret_cast<const uint32_t *>(base + b.units_off),
+                                                       b.n_units, base + b.marks_off, s),
+                         "unpack launch");
+}
 
 bcf_status bcf_decode_batch(const bcf_material *mats, uint32_t n_mats, bcf_precision p, void *ws,
                             const float *queries, const uint32_t *offsets, uint32_t n_total, float *out,

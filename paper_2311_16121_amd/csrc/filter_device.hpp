@@ -63,6 +63,33 @@ struct Footprint {
     float w00, w10, w01, w11;
 };
 
+// The integer texel coordinates of a level's bilinear footprint: columns x0
+// and x0 + 1 (x0 + 1 = w is the wrap column, a copy of column 0), rows y0 and
+// y1, and the fractional parts. Shared by the filters and the batch's marking
+// of the blocks a set of queries touches, so both take the same taps.
+struct TapCoords {
+    uint32_t x0, y0, y1, wm;
+    float fx, fy;
+};
+
+__device__ __forceinline__ TapCoords tap_coords(uint4 e, float uf, float vf)
+{
+#pragma clang fp contract(off)
+    // copy the fields to plain integers before reinterpreting them
+    const uint32_t ew = e.x, eh = e.y, masks = e.z;
+    const float x = fmaf(uf, __builtin_bit_cast(float, ew), -0.5f);
+    const float y = fmaf(vf, __builtin_bit_cast(float, eh), -0.5f);
+    TapCoords t;
+    t.fx = __builtin_amdgcn_fractf(x);
+    t.fy = __builtin_amdgcn_fractf(y);
+    t.wm = masks & 0xFFFFu;
+    const uint32_t hm = masks >> 16;
+    t.x0 = (uint32_t)(int)floorf(x) & t.wm;                     // -1 wraps to w-1
+    t.y0 = (uint32_t)(int)floorf(y) & hm;
+    t.y1 = (t.y0 + 1u) & hm;
+    return t;
+}
+
 // UNIT: bytes per texel slot of the scratch (8; 32 for an interleaved one,
 // whose LUT offsets count 32-byte positions)
 template <uint32_t UNIT = 8>
@@ -71,16 +98,11 @@ __device__ __forceinline__ Footprint footprint(uint4 e, float uf, float vf, floa
     // every product and sum below is rounded as written, whichever kernel
     // this is inlined into, so all decode kernels filter bit-identically
 #pragma clang fp contract(off)
-    // copy the fields to plain integers before reinterpreting them
-    const uint32_t ew = e.x, eh = e.y, masks = e.z, first = e.w;
-    const float x = fmaf(uf, __builtin_bit_cast(float, ew), -0.5f);
-    const float y = fmaf(vf, __builtin_bit_cast(float, eh), -0.5f);
-    const float fx = __builtin_amdgcn_fractf(x), fy = __builtin_amdgcn_fractf(y);
-    const uint32_t wm = masks & 0xFFFFu, hm = masks >> 16;
-    const uint32_t x0 = (uint32_t)(int)floorf(x) & wm;          // -1 wraps to w-1
-    const uint32_t y0 = (uint32_t)(int)floorf(y) & hm;
-    const uint32_t y1 = (y0 + 1u) & hm;
-    const uint32_t lw2 = __builtin_popcount(wm);                // log2 w
+    const uint32_t first = e.w;
+    const TapCoords t = tap_coords(e, uf, vf);
+    const float fx = t.fx, fy = t.fy;
+    const uint32_t x0 = t.x0, y0 = t.y0, y1 = t.y1;
+    const uint32_t lw2 = __builtin_popcount(t.wm);              // log2 w
     // row y starts at y * (w + 2) = (y << log2 w) + 2 y
     Footprint f;
     f.o0 = ((y0 << lw2) + 2u * y0 + x0 + first) * UNIT;

@@ -496,6 +496,7 @@ struct BatchMat {
     float levels_bias[2 * kMaxTextures];
     uint64_t scratch_off, weights_off;     // bytes from the workspace start
     uint32_t scratch_bytes, stride, shared, interleaved;   // interleaved: as MaterialDesc
+    uint32_t seg_chunk[kMaxLevels];        // interleaved: first unpack chunk of each level's segment
 };
 
 struct BatchArgs {

@@ -94,6 +94,18 @@ struct UnpackSeg {
 // every segment of a batch in one launch (segs in device memory, by first chunk)
 // chunk_seg[c] = the segment of chunk c (n_chunks entries)
 hipError_t launch_predecode_batch(const UnpackSeg *segs, const uint32_t *chunk_seg, uint32_t n_chunks, hipStream_t s);
+// Unpacks the marked block positions of the interleaved segments and every
+// chunk of the others: units[u] = first chunk of unit u (a window of up to
+// four chunks of one interleaved segment, or one chunk of another segment).
+hipError_t launch_predecode_touched(const UnpackSeg *segs, const uint32_t *chunk_seg, uint32_t n_seg,
+                                    uint32_t n_chunks, const uint32_t *units, uint32_t n_units, const uint8_t *marks,
+                                    hipStream_t s);
+// Clears marks[0..mark_bytes) (a multiple of 16), fills the batch's item
+// prefix, and marks the block positions the queries of the interleaved
+// materials read.
+hipError_t launch_batch_mark(void *ws, size_t table_off, size_t items_off, const float *queries,
+                             const uint32_t *offsets, uint32_t n_mats, uint32_t n_total, uint8_t *marks,
+                             size_t mark_bytes, hipStream_t s);
 
 // operand elements and rows of layer l in the workspace (kernels.hip owns the layout)
 size_t mlp_layer_elems(const MlpShape &s, uint32_t l, MlpKind k);
@@ -131,6 +143,7 @@ hipError_t launch_filter_mlp(const MaterialDesc &m, const MlpShape &sh, MlpKind 
 // the batch workspace.
 struct BatchSlot {
     size_t scratch_off, scratch_bytes, weights_off;
+    uint32_t seg_chunk[kMaxLevels];    // interleaved: first unpack chunk of each level's segment
 };
 
 size_t batch_table_bytes(uint32_t n_mats);

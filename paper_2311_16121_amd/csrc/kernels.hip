@@ -99,20 +99,25 @@ __device__ __forceinline__ void store_pair(uint2 *dst, uint2 t0, uint2 t1)
 
 // One chunk (256 lanes) of one unpack segment into the texel scratch. The
 // whole workgroup calls it (it synchronises once); `palette` and `slots` are
-// the workgroup's LDS, `table` the mode table.
+// the workgroup's LDS, `table` the mode table. With `list` (LDS, interleaved
+// segments only) the chunk is instead the block positions list[0..n_list)
+// of the segment (at most 64), four lanes each; `chunk` is then unused.
 template <bool SIGNED>
 __device__ __forceinline__ void unpack_chunk(const UnpackSeg &sg, uint32_t chunk, const uint32_t *table,
-                                             uint2 (*palette)[256], uint2 *slots)
+                                             uint2 (*palette)[256], uint2 *slots, const uint32_t *list = nullptr,
+                                             uint32_t n_list = 0)
 {
     // interleaved scratch: lane = 4 * block + pyramid, all four pyramids of a
     // level in one segment; otherwise lane = block of the segment's pyramid
     const uint32_t il = sg.flags & kSegInterleaved;
-    const uint32_t li = chunk * 256 + threadIdx.x;
+    const uint32_t li = list ? threadIdx.x : chunk * 256 + threadIdx.x;
     const uint32_t lw = sg.lw, lh = sg.lh;
     const uint32_t bx = (lw + 3) / 4, by = (lh + 3) / 4, n_blk = bx * by;
     const uint32_t first = chunk * 256;         // this chunk's first block (per-pyramid layout)
-    const uint32_t bi = il ? li >> 2 : li;
-    if (bi < n_blk) {
+    // a lane's block and whether it has one
+    const bool have = list ? (threadIdx.x >> 2) < n_list : (il ? li >> 2 : li) < n_blk;
+    const uint32_t bi = list ? (have ? list[threadIdx.x >> 2] : 0u) : (il ? li >> 2 : li);
+    if (have) {
         // the lane's pyramid by selects (an indexed pointer array would sit
         // in private memory)
         const uint32_t pyr = il ? (li & 3u) : 0u;
@@ -150,8 +155,9 @@ __device__ __forceinline__ void unpack_chunk(const UnpackSeg &sg, uint32_t chunk
         const uint32_t chunk8 = lane & 7u, pp = 2 * (lane & 1u), cpos = chunk8 >> 1;
         for (uint32_t h = 0; h < 2; ++h) {
             const uint32_t blw = 8 * h + (lane >> 3);                     // block within the wave
-            const uint32_t bj = ((li - lane) >> 2) + blw;                 // its index in the level
-            if (bj >= n_blk) continue;
+            const uint32_t p = (wave0 >> 2) + blw;                        // within the chunk
+            if (list ? p >= n_list : ((li - lane) >> 2) + blw >= n_blk) continue;
+            const uint32_t bj = list ? list[p] : ((li - lane) >> 2) + blw;   // its index in the level
             const uint32_t lb = wave0 + 4 * blw + pp;                     // LDS lane of pyramid pp
             const uint32_t x0 = 4 * (bj % bx), y0 = 4 * (bj / bx);
             uint2 *dst = sg.texels + pp;
@@ -274,6 +280,70 @@ __global__ void __launch_bounds__(256) k_predecode_batch(const UnpackSeg *segs, 
         else unpack_chunk<false>(sg, c - sg.wg0, table, palette, slots);
         __syncthreads();                          // palette and slots are reused by the next chunk
     }
+}
+
+// The blocks of a batch that a set of queries touches, unpacked in one
+// launch. Workgroup u takes unit units[u]: for a position-interleaved
+// segment, a window of up to four chunks (256 block positions) whose marked
+// positions it gathers in LDS and unpacks, 64 positions per pass (most
+// windows need one pass with one or two busy waves); for any other segment,
+// one whole chunk. marks[64 c + p] != 0: position p of chunk c is needed.
+__global__ void __launch_bounds__(256) k_predecode_touched(const UnpackSeg *segs, const uint32_t *chunk_seg,
+                                                           uint32_t n_seg, uint32_t n_chunks, const uint32_t *units,
+                                                           uint32_t n_units, const uint8_t *marks)
+{
+    __shared__ uint32_t table[kTableWords];
+    __shared__ uint2 palette[16][256];
+    __shared__ uint2 slots[256];
+    __shared__ uint32_t list[256];
+    __shared__ uint32_t counts[4];
+    load_table(table);
+    const uint32_t t = threadIdx.x, lane = t & 63u, wv = t >> 6;
+    for (uint32_t u = blockIdx.x; u < n_units; u += gridDim.x) {
+        const uint32_t c0 = units[u];
+        const uint32_t sidx = chunk_seg[c0];
+        const UnpackSeg sg = segs[sidx];
+        const bool sgn = (sg.flags & kSegSigned) != 0;
+        if (!(sg.flags & kSegInterleaved)) {
+            if (sgn) unpack_chunk<true>(sg, c0 - sg.wg0, table, palette, slots);
+            else unpack_chunk<false>(sg, c0 - sg.wg0, table, palette, slots);
+            __syncthreads();                      // palette and slots are reused by the next unit
+            continue;
+        }
+        const uint32_t end = sidx + 1 < n_seg ? segs[sidx + 1].wg0 : n_chunks;
+        const uint32_t nc = min(4u, end - c0);
+        const bool m = t < 64u * nc && marks[64ull * c0 + t] != 0;
+        const uint64_t bal = __ballot(m);
+        if (lane == 0) counts[wv] = (uint32_t)__popcll(bal);
+        __syncthreads();
+        uint32_t before = 0, total = 0;
+#pragma unroll
+        for (uint32_t w = 0; w < 4; ++w) {
+            const uint32_t c = counts[w];
+            before += w < wv ? c : 0u;
+            total += c;
+        }
+        const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+        if (m) list[before + rank] = 64u * (c0 - sg.wg0) + t;       // the position within the segment
+        __syncthreads();
+        for (uint32_t p0 = 0; p0 < total; p0 += 64) {
+            const uint32_t n = min(64u, total - p0);
+            if (sgn) unpack_chunk<true>(sg, 0, table, palette, slots, list + p0, n);
+            else unpack_chunk<false>(sg, 0, table, palette, slots, list + p0, n);
+            __syncthreads();
+        }
+    }
+}
+
+hipError_t launch_predecode_touched(const UnpackSeg *segs, const uint32_t *chunk_seg, uint32_t n_seg,
+                                    uint32_t n_chunks, const uint32_t *units, uint32_t n_units, const uint8_t *marks,
+                                    hipStream_t s)
+{
+    if (n_units == 0) return hipSuccess;
+    const unsigned grid = std::min<unsigned>(n_units, 1u << 22);
+    k_predecode_touched<<<grid, 256, 0, s>>>(segs, chunk_seg, n_seg, n_chunks, units, n_units, marks);
+    return hipGetLastError();
 }
 
 hipError_t launch_predecode_batch(const UnpackSeg *segs, const uint32_t *chunk_seg, uint32_t n_chunks, hipStream_t s)
@@ -591,6 +661,85 @@ __global__ void k_batch_items(BatchArgs a)
     a.items[a.n_mats] = acc;
 }
 
+// Marks, for the position-interleaved materials of a batch, the block
+// positions the queries' footprints read: the same work items, levels and taps
+// as k_batch (items of 64 queries; a lane past a material's queries reads the
+// query (0, 0, 0), as k_batch's does). marks[64 c + p] = 1 for position p of
+// unpack chunk c. Byte stores: concurrent marks of one position store the
+// same value.
+__global__ void __launch_bounds__(256) k_batch_mark(BatchArgs a, uint8_t *marks)
+{
+    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+    const uint32_t total = a.items[a.n_mats];
+    for (uint32_t it = blockIdx.x * 4 + wv; it < total; it += gridDim.x * 4) {
+        uint32_t lo = 0, hi = a.n_mats;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (a.items[mid] <= it) lo = mid;
+            else hi = mid;
+        }
+        lo = uniform(lo);
+        const BatchMat &M = a.mats[lo];
+        if (!uniform(M.interleaved)) continue;    // unpacked whole
+        uint32_t q0, n_k;
+        batch_range(a, lo, q0, n_k);
+        const __amdgpu_buffer_rsrc_t rq = make_rsrc(a.queries + 3ull * uniform(q0), uniform(n_k) * 12u);
+        const Query q = load_query(rq, (it - uniform(a.items[lo])) * 64 + lane);
+        const float uf = q.u - floorf(q.u), vf = q.v - floorf(q.v);
+        const LevelSel ls = select_levels(q.s, M.levels_bias[1], __builtin_bit_cast(uint32_t, M.levels_bias[0]));
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const uint32_t l = k ? ls.l1 : ls.l0;
+            const uint4 e = M.lut.e[0][l];
+            const TapCoords tc = tap_coords(e, uf, vf);
+            const uint32_t w = tc.wm + 1u, bxn = (w + 3u) >> 2;
+            const uint32_t xa = tc.x0 >> 2, xb = ((tc.x0 + 1u) & tc.wm) >> 2;   // column w is column 0
+            const uint32_t ya = tc.y0 >> 2, yb = tc.y1 >> 2;
+            uint8_t *mk = marks + 64ull * M.seg_chunk[l];
+            mk[ya * bxn + xa] = 1;
+            mk[ya * bxn + xb] = 1;
+            mk[yb * bxn + xa] = 1;
+            mk[yb * bxn + xb] = 1;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_fill_u32x4(u32x4_t *p, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = (u32x4_t){0u, 0u, 0u, 0u};
+}
+
+hipError_t launch_batch_mark(void *ws, size_t table_off, size_t items_off, const float *queries,
+                             const uint32_t *offsets, uint32_t n_mats, uint32_t n_total, uint8_t *marks,
+                             size_t mark_bytes, hipStream_t s)
+{
+    // clear with a kernel (a graph replays it reliably), then the items, then the marks
+    const size_t n16 = mark_bytes / 16;
+    if (n16) {
+        k_fill_u32x4<<<(unsigned)std::min<size_t>((n16 + 255) / 256, 8192), 256, 0, s>>>(
+            reinterpret_cast<u32x4_t *>(marks), n16);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    BatchArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.ws = static_cast<const uint8_t *>(ws);
+    a.mats = reinterpret_cast<const BatchMat *>(static_cast<uint8_t *>(ws) + table_off);
+    a.offsets = offsets;
+    a.items = reinterpret_cast<uint32_t *>(static_cast<uint8_t *>(ws) + items_off);
+    a.queries = queries;
+    a.n_mats = n_mats;
+    a.n_total = n_total;
+    k_batch_items<<<1, 64, 0, s>>>(a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // one wave per item of 64 queries; at most 2^24 items
+    const unsigned grid = std::min<unsigned>(std::max<unsigned>((n_total + 255u) / 256u + n_mats, 1u), 65536u);
+    k_batch_mark<<<grid, 256, 0, s>>>(a, marks);
+    return hipGetLastError();
+}
+
 hipError_t write_batch_table(const MaterialDesc *mats, const BatchSlot *slots, uint32_t n_mats, uint32_t out_dim,
                              const WsHeader &header, void *ws, size_t table_off, const UnpackSeg *segs,
                              uint32_t n_seg, size_t segs_off, const uint32_t *chunk_seg, uint32_t n_chunks,
@@ -624,6 +773,7 @@ hipError_t write_batch_table(const MaterialDesc *mats, const BatchSlot *slots, u
         b.stride = a.stride;
         b.shared = shared ? 1u : 0u;
         b.interleaved = mats[k].interleaved;
+        std::memcpy(b.seg_chunk, slots[k].seg_chunk, sizeof b.seg_chunk);
     }
     hipError_t e = hipMemcpyAsync(ws, host.data(), host.size(), hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return e;

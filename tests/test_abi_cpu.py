@@ -244,6 +244,17 @@ def test_batch_validation(bcf):
         assert bcf.lib.bcf_decode_batch(arr, 2, 1, C.c_void_p(FAKE), C.c_void_p(FAKE), C.c_void_p(FAKE), 10,
                                         C.c_void_p(FAKE), C.byref(p), None) == 1
         assert msg in bcf.lib.bcf_last_error().decode()
+    # the touched-blocks unpack: argument checks before any launch
+    touched = bcf.lib.bcf_unpack_batch_touched
+    assert touched(arr, 2, C.c_void_p(FAKE), C.c_void_p(FAKE), None, 10, None) == 1
+    assert "offsets" in bcf.lib.bcf_last_error().decode()
+    assert touched(arr, 2, C.c_void_p(FAKE), C.c_void_p(FAKE + 2), C.c_void_p(FAKE), 10, None) == 1
+    assert "queries" in bcf.lib.bcf_last_error().decode()
+    assert touched(arr, 2, C.c_void_p(FAKE + 8), C.c_void_p(FAKE), C.c_void_p(FAKE), 10, None) == 1
+    assert "workspace" in bcf.lib.bcf_last_error().decode()
+    assert touched(arr, 2, C.c_void_p(FAKE), C.c_void_p(FAKE), C.c_void_p(FAKE), 10, None) == 1
+    assert "bcf_prepare_batch" in bcf.lib.bcf_last_error().decode()
+    assert touched(arr, 0, C.c_void_p(FAKE), C.c_void_p(FAKE), C.c_void_p(FAKE), 10, None) == 1
 
 
 def test_workspace_not_filled_by_prepare_is_rejected(bcf):

@@ -7,7 +7,9 @@ Bars:
   * sampled rows against the oracle: FP32 <= 1e-5, FP16 <= 2e-3 absolute
     (bounded-feature materials);
   * rows that no material covers are left untouched;
-  * graph replays equal the eager decode of the queries present at replay time.
+  * graph replays equal the eager decode of the queries present at replay time;
+  * after unpacking only the blocks the queries touch (on a workspace whose
+    other texels are NaN), the decode equals the single-material decodes.
 """
 import numpy as np
 import pytest
@@ -164,6 +166,61 @@ def test_batch_plans_agree_and_tuner_returns_one(bcf, shared_only):
     assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
 
 
+def special_queries(n, g, top):
+    """Uniform queries with wrap, clamp and NaN cases mixed in."""
+    q = synth.uniform_queries(n, g, top)
+    k = min(n, 12)
+    q[:k] = np.array([[0.0, 0.0, 0.0], [1.0, 1.0, top], [-0.25, 1.75, -3.0], [0.999999, 0.5, 99.0],
+                      [0.5, 0.0, 0.5], [3.5, -2.25, 1.0], [np.nan, 0.5, 1.0], [0.5, 0.5, np.nan],
+                      [0.0, 0.999, top + 0.5], [1e-7, 1e-7, 0.999], [0.75, 0.125, 2.5], [0.5, 0.5, 0.0]],
+                     np.float32)[:k]
+    return q
+
+
+@pytest.mark.parametrize("precision", ["FP16", "FP32"])
+def test_touched_unpack_equals_full_unpack(bcf, precision):
+    # a workspace of all-ones bytes: every texel the touched unpack leaves
+    # alone is a NaN half, so a decode that read one would not match
+    host, mats, qs, offsets = make_batch(bcf, seed=68)
+    g = synth.rng(69)
+    qs = [special_queries(len(q), g, float(max(levels) - 1)) for q, (_, levels, _, _) in zip(qs, SHAPES)]
+    prec = bcf.Precision[precision]
+    batch = bcf.Batch(mats, prec, ws_fill=0xFF)
+    q_all, offs = dev(np.concatenate(qs)), dev(offsets)
+    batch.unpack_touched(q_all, offs)
+    out = batch.decode(q_all, offs).cpu().numpy()
+    for k, m in enumerate(mats):
+        if len(qs[k]) == 0:
+            continue
+        ref = bcf.decode(m, bcf.prepare(m, prec), dev(qs[k]), prec).cpu().numpy()
+        got = out[offsets[k]: offsets[k + 1]]
+        assert np.array_equal(got.view(np.uint32), ref.view(np.uint32)), k
+    # a second, smaller set of queries after the first
+    qs2 = [q[: len(q) // 3] for q in qs]
+    offsets2 = np.concatenate([[0], np.cumsum([len(q) for q in qs2])]).astype(np.int32)
+    q2 = dev(np.concatenate(qs2))
+    batch.unpack_touched(q2, dev(offsets2))
+    out2 = batch.decode(q2, dev(offsets2)).cpu().numpy()
+    assert np.array_equal(out2.view(np.uint32), out[np.concatenate(
+        [np.arange(offsets[k], offsets[k] + len(qs2[k])) for k in range(len(qs))])].view(np.uint32))
+    log(f"touched unpack {precision}: every material equals its single decode")
+
+
+def test_touched_unpack_with_clamped_offsets(bcf):
+    host, mats, qs, _ = make_batch(bcf, SHAPES[:3], seed=70)
+    batch = bcf.Batch(mats, bcf.Precision.FP16, ws_fill=0xFF)
+    n_total = 5000
+    q_all = dev(synth.uniform_queries(n_total, synth.rng(71), 6.0))
+    ws = [bcf.prepare(m, bcf.Precision.FP16) for m in mats]
+    offs = dev(np.array([100, 1100, 900, 2 ** 31 - 1], np.int32))
+    batch.unpack_touched(q_all, offs)
+    o = batch.decode(q_all, offs).cpu().numpy()
+    ref0 = bcf.decode(mats[0], ws[0], q_all[100:900], bcf.Precision.FP16).cpu().numpy()
+    ref2 = bcf.decode(mats[2], ws[2], q_all[1100:5000], bcf.Precision.FP16).cpu().numpy()
+    assert np.array_equal(o[100:900].view(np.uint32), ref0.view(np.uint32))
+    assert np.array_equal(o[1100:5000].view(np.uint32), ref2.view(np.uint32))
+
+
 def test_batch_graph_capture_replays(bcf):
     host, mats, qs, offsets = make_batch(bcf, seed=65)
     batch = bcf.Batch(mats, bcf.Precision.FP16)
@@ -180,6 +237,18 @@ def test_batch_graph_capture_replays(bcf):
             batch.unpack()
             batch.decode(q_static, offs, out=out_static)
     torch.cuda.synchronize()
+    # the touched unpack in a graph of its own, on a workspace of all-ones bytes
+    tbatch = bcf.Batch(mats, bcf.Precision.FP16, ws_fill=0xFF)
+    tout = torch.empty_like(out_static)
+    tbatch.unpack_touched(q_static, offs)
+    tbatch.decode(q_static, offs, out=tout)
+    torch.cuda.synchronize()
+    tgraph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(tgraph, stream=side):
+            tbatch.unpack_touched(q_static, offs)
+            tbatch.decode(q_static, offs, out=tout)
+    torch.cuda.synchronize()
     g = synth.rng(66)
     a = torch.randn(512, 512, device="cuda")
     for replay in range(4):
@@ -187,8 +256,10 @@ def test_batch_graph_capture_replays(bcf):
         q_static.copy_(fresh)
         b = a @ a                                           # eager work between replays
         graph.replay()
+        tgraph.replay()
         torch.cuda.synchronize()
         eager = batch.decode(fresh, offs).cpu().numpy()
         assert np.array_equal(out_static.cpu().numpy().view(np.uint32), eager.view(np.uint32)), replay
+        assert np.array_equal(tout.cpu().numpy().view(np.uint32), eager.view(np.uint32)), replay
         assert torch.isfinite(b).all()
-    log("graph: 4 replays equal the eager decode")
+    log("graph: 4 replays equal the eager decode (full and touched unpack)")
