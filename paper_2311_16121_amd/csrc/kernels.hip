@@ -695,11 +695,14 @@ __global__ void __launch_bounds__(256) k_batch_mark(BatchArgs a, uint8_t *marks)
             const uint32_t w = tc.wm + 1u, bxn = (w + 3u) >> 2;
             const uint32_t xa = tc.x0 >> 2, xb = ((tc.x0 + 1u) & tc.wm) >> 2;   // column w is column 0
             const uint32_t ya = tc.y0 >> 2, yb = tc.y1 >> 2;
+            // most footprints lie in one block: store each distinct position once
             uint8_t *mk = marks + 64ull * M.seg_chunk[l];
             mk[ya * bxn + xa] = 1;
-            mk[ya * bxn + xb] = 1;
-            mk[yb * bxn + xa] = 1;
-            mk[yb * bxn + xb] = 1;
+            if (xb != xa) mk[ya * bxn + xb] = 1;
+            if (yb != ya) {
+                mk[yb * bxn + xa] = 1;
+                if (xb != xa) mk[yb * bxn + xb] = 1;
+            }
         }
     }
 }
