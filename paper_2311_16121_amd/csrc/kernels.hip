@@ -666,44 +666,80 @@ __global__ void k_batch_items(BatchArgs a)
 // as k_batch (items of 64 queries; a lane past a material's queries reads the
 // query (0, 0, 0), as k_batch's does). marks[64 c + p] = 1 for position p of
 // unpack chunk c. Byte stores: concurrent marks of one position store the
-// same value.
+// same value. Each wave walks a contiguous range of items with its current
+// material's level table in LDS, loading the next item's queries while it
+// marks the current one's.
 __global__ void __launch_bounds__(256) k_batch_mark(BatchArgs a, uint8_t *marks)
 {
-    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+    __shared__ uint4 lut[4][kMaxLevels];
+    __shared__ uint32_t segc[4][kMaxLevels];
+    const uint32_t lane = threadIdx.x & 63u, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t total = a.items[a.n_mats];
-    for (uint32_t it = blockIdx.x * 4 + wv; it < total; it += gridDim.x * 4) {
-        uint32_t lo = 0, hi = a.n_mats;
-        while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (a.items[mid] <= it) lo = mid;
-            else hi = mid;
+    const uint32_t waves = gridDim.x * 4, w = blockIdx.x * 4 + wv;
+    const uint32_t first = (uint32_t)((uint64_t)total * w / waves), end = (uint32_t)((uint64_t)total * (w + 1) / waves);
+    if (first >= end) return;
+    uint32_t lo = 0, hi = a.n_mats;                 // the material of `first`
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (a.items[mid] <= first) lo = mid;
+        else hi = mid;
+    }
+    lo = uniform(lo);
+    uint32_t base = 0, next = 0, interleaved = 0;
+    float lb0 = 0.0f, lb1 = 0.0f;
+    __amdgpu_buffer_rsrc_t rq = make_rsrc(a.queries, 0);
+    auto enter = [&](uint32_t k) {                  // material k becomes current
+        const BatchMat &M = a.mats[k];
+        if (lane < (uint32_t)kMaxLevels) {
+            lut[wv][lane] = M.lut.e[0][lane];
+            segc[wv][lane] = M.seg_chunk[lane];
         }
-        lo = uniform(lo);
-        const BatchMat &M = a.mats[lo];
-        if (!uniform(M.interleaved)) continue;    // unpacked whole
+        interleaved = uniform(M.interleaved);
+        lb0 = __builtin_bit_cast(float, uniform(__builtin_bit_cast(uint32_t, M.levels_bias[0])));
+        lb1 = __builtin_bit_cast(float, uniform(__builtin_bit_cast(uint32_t, M.levels_bias[1])));
         uint32_t q0, n_k;
-        batch_range(a, lo, q0, n_k);
-        const __amdgpu_buffer_rsrc_t rq = make_rsrc(a.queries + 3ull * uniform(q0), uniform(n_k) * 12u);
-        const Query q = load_query(rq, (it - uniform(a.items[lo])) * 64 + lane);
-        const float uf = q.u - floorf(q.u), vf = q.v - floorf(q.v);
-        const LevelSel ls = select_levels(q.s, M.levels_bias[1], __builtin_bit_cast(uint32_t, M.levels_bias[0]));
+        batch_range(a, k, q0, n_k);
+        rq = make_rsrc(a.queries + 3ull * uniform(q0), uniform(n_k) * 12u);
+        base = uniform(a.items[k]);
+        next = uniform(a.items[k + 1]);
+        wave_lds_sync();
+    };
+    enter(lo);
+    Query q = load_query(rq, (first - base) * 64 + lane);
+    for (uint32_t it = first; it < end; ++it) {
+        const uint32_t nx = it + 1;
+        const bool same = nx < next;
+        Query qn = Query{0.0f, 0.0f, 0.0f};
+        if (nx < end && same) qn = load_query(rq, (nx - base) * 64 + lane);
+        if (interleaved) {
+            const float uf = q.u - floorf(q.u), vf = q.v - floorf(q.v);
+            const LevelSel ls = select_levels(q.s, lb1, __builtin_bit_cast(uint32_t, lb0));
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            const uint32_t l = k ? ls.l1 : ls.l0;
-            const uint4 e = M.lut.e[0][l];
-            const TapCoords tc = tap_coords(e, uf, vf);
-            const uint32_t w = tc.wm + 1u, bxn = (w + 3u) >> 2;
-            const uint32_t xa = tc.x0 >> 2, xb = ((tc.x0 + 1u) & tc.wm) >> 2;   // column w is column 0
-            const uint32_t ya = tc.y0 >> 2, yb = tc.y1 >> 2;
-            // most footprints lie in one block: store each distinct position once
-            uint8_t *mk = marks + 64ull * M.seg_chunk[l];
-            mk[ya * bxn + xa] = 1;
-            if (xb != xa) mk[ya * bxn + xb] = 1;
-            if (yb != ya) {
-                mk[yb * bxn + xa] = 1;
-                if (xb != xa) mk[yb * bxn + xb] = 1;
+            for (int k = 0; k < 2; ++k) {
+                const uint32_t l = k ? ls.l1 : ls.l0;
+                const TapCoords tc = tap_coords(lut[wv][l], uf, vf);
+                const uint32_t bxn = (tc.wm + 4u) >> 2;                            // (w + 3) / 4
+                const uint32_t xa = tc.x0 >> 2, xb = ((tc.x0 + 1u) & tc.wm) >> 2;   // column w is column 0
+                const uint32_t ya = tc.y0 >> 2, yb = tc.y1 >> 2;
+                // most footprints lie in one block: store each distinct position once
+                uint8_t *mk = marks + 64ull * segc[wv][l];
+                mk[ya * bxn + xa] = 1;
+                if (xb != xa) mk[ya * bxn + xb] = 1;
+                if (yb != ya) {
+                    mk[yb * bxn + xa] = 1;
+                    if (xb != xa) mk[yb * bxn + xb] = 1;
+                }
             }
         }
+        if (nx < end && !same) {                    // the next item starts another material
+            wave_lds_sync();                        // this item's LDS reads are done
+            uint32_t k = lo + 1;
+            while (k + 1 < a.n_mats && a.items[k + 1] <= nx) ++k;   // past empty materials
+            lo = uniform(k);
+            enter(lo);
+            qn = load_query(rq, (nx - base) * 64 + lane);
+        }
+        q = qn;
     }
 }
 
@@ -737,8 +773,10 @@ hipError_t launch_batch_mark(void *ws, size_t table_off, size_t items_off, const
     k_batch_items<<<1, 64, 0, s>>>(a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    // one wave per item of 64 queries; at most 2^24 items
-    const unsigned grid = std::min<unsigned>(std::max<unsigned>((n_total + 255u) / 256u + n_mats, 1u), 65536u);
+    // waves walk contiguous ranges of at least 16 items (1024 queries), at
+    // most 8192 waves (what the chip keeps resident)
+    const uint32_t items = (uint32_t)(((uint64_t)n_total + 63u) / 64u) + n_mats;
+    const unsigned grid = std::min<unsigned>(std::max<unsigned>((items + 63u) / 64u, 1u), 2048u);
     k_batch_mark<<<grid, 256, 0, s>>>(a, marks);
     return hipGetLastError();
 }
