@@ -48,6 +48,18 @@ __host__ __device__ __forceinline__ uint32_t funnel(uint32_t hi, uint32_t lo, ui
     return (uint32_t)((((uint64_t)hi << 32) | lo) >> s);
 }
 
+// lo | hi << 16 for 16-bit lo and hi. On the GPU one byte permute: written as
+// a shift, the compiler folds the shift into the multiply that produced hi,
+// turning a full-rate 24-bit multiply into a quarter-rate 32-bit one.
+__host__ __device__ __forceinline__ uint32_t pack_lo_hi(uint32_t lo, uint32_t hi)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_perm(hi, lo, 0x05040100u);
+#else
+    return (lo & 0xFFFFu) | (hi << 16);
+#endif
+}
+
 // reverse the low k bits of v (k = 0..32)
 __host__ __device__ __forceinline__ uint32_t reverse_low(uint32_t v, uint32_t k)
 {
@@ -336,7 +348,7 @@ __host__ __device__ __forceinline__ void bc6h_palette(const Bc6hHeader &h, uint3
                 ch[c] = (((m & 0xFFFFFFu) * 31u) >> 5) | (v < 0 ? 0x8000u : 0u);    // |v| <= 0x7FFF
             }
         }
-        pal[j][0] = ch[0] | (ch[1] << 16);
+        pal[j][0] = pack_lo_hi(ch[0], ch[1]);
         pal[j][1] = ch[2];
     }
 }
@@ -346,6 +358,35 @@ __host__ __device__ __forceinline__ uint32_t bc6h_slot(const Bc6hHeader &h, uint
 {
     const uint32_t i = (uint32_t)(h.idx >> (h.ib * t)) & ((1u << h.ib) - 1u);
     return h.ib == 3 ? ((((h.mask >> t) & 1u) << 3) | i) : i;
+}
+
+// Eight 3-bit fields (bits 3k..3k+2 of x) moved to 4-bit nibbles (bits 4k..4k+2).
+__host__ __device__ __forceinline__ uint32_t spread3to4(uint32_t x)
+{
+    x = (x & 0x00000FFFu) | ((x & 0x00FFF000u) << 4);      // fields 4..7 up by 4
+    x = (x & 0x003F003Fu) | ((x & 0x0FC00FC0u) << 2);      // fields 2, 3, 6, 7 up by 2
+    return (x & 0x07070707u) | ((x & 0x38383838u) << 1);   // fields 1, 3, 5, 7 up by 1
+}
+
+// Eight bits (bit k of x) moved to bit 4k.
+__host__ __device__ __forceinline__ uint32_t spread1to4(uint32_t x)
+{
+    x = (x & 0x0000000Fu) | ((x & 0x000000F0u) << 12);     // bits 4..7 to 16..19
+    x = (x & 0x00030003u) | ((x & 0x000C000Cu) << 6);      // bits 2, 3 (18, 19) up by 6
+    return (x & 0x01010101u) | ((x & 0x02020202u) << 3);   // bits 1 (9, 17, 25) up by 3
+}
+
+// Palette entries of all 16 texels, four bits each: texel t's bc6h_slot at
+// bits 4t..4t+3 of s0 (t < 8) or s1 (t >= 8).
+__host__ __device__ __forceinline__ void bc6h_slots(const Bc6hHeader &h, uint32_t &s0, uint32_t &s1)
+{
+    if (h.ib == 4) {                          // one subset: the 4-bit indices are the slots
+        s0 = (uint32_t)h.idx;
+        s1 = (uint32_t)(h.idx >> 32);
+    } else {                                  // two subsets: 3-bit index | subset << 3
+        s0 = spread3to4((uint32_t)h.idx & 0xFFFFFFu) | (spread1to4(h.mask & 0xFFu) << 3);
+        s1 = spread3to4((uint32_t)(h.idx >> 24) & 0xFFFFFFu) | (spread1to4((h.mask >> 8) & 0xFFu) << 3);
+    }
 }
 
 }  // namespace bcf

@@ -113,6 +113,8 @@ __device__ __forceinline__ void unpack_chunk(const UnpackSeg &sg, uint32_t chunk
     const uint32_t li = list ? threadIdx.x : chunk * 256 + threadIdx.x;
     const uint32_t lw = sg.lw, lh = sg.lh;
     const uint32_t bx = (lw + 3) / 4, by = (lh + 3) / 4, n_blk = bx * by;
+    // level sizes are powers of two: block bj sits at (bj & bxm, bj >> bxs)
+    const uint32_t bxm = bx - 1u, bxs = (uint32_t)__builtin_ctz(bx);
     const uint32_t first = chunk * 256;         // this chunk's first block (per-pyramid layout)
     // a lane's block and whether it has one
     const bool have = list ? (threadIdx.x >> 2) < n_list : (il ? li >> 2 : li) < n_blk;
@@ -129,12 +131,8 @@ __device__ __forceinline__ void unpack_chunk(const UnpackSeg &sg, uint32_t chunk
         bc6h_palette<SIGNED>(h, pal);
 #pragma unroll
         for (int j = 0; j < 16; ++j) palette[j][threadIdx.x] = make_uint2(pal[j][0], pal[j][1]);
-        uint32_t s0 = 0, s1 = 0;
-#pragma unroll
-        for (uint32_t t = 0; t < 8; ++t) {
-            s0 |= bc6h_slot(h, t) << (4 * t);
-            s1 |= bc6h_slot(h, t + 8) << (4 * t);
-        }
+        uint32_t s0, s1;
+        bc6h_slots(h, s0, s1);
         slots[threadIdx.x] = make_uint2(s0, s1);
     }
     __syncthreads();
@@ -159,19 +157,20 @@ __device__ __forceinline__ void unpack_chunk(const UnpackSeg &sg, uint32_t chunk
             if (list ? p >= n_list : ((li - lane) >> 2) + blw >= n_blk) continue;
             const uint32_t bj = list ? list[p] : ((li - lane) >> 2) + blw;   // its index in the level
             const uint32_t lb = wave0 + 4 * blw + pp;                     // LDS lane of pyramid pp
-            const uint32_t x0 = 4 * (bj % bx), y0 = 4 * (bj / bx);
+            const uint32_t x0 = 4 * (bj & bxm), y0 = 4 * (bj >> bxs);
             uint2 *dst = sg.texels + pp;
             for (uint32_t r = 0; r < 4; ++r) {
                 if (y0 + r >= lh) break;
-                uint2 *row = dst + (size_t)kMaxTextures * (y0 + r) * pitch;
+                // position index within the level (below 2^31: levels are at most 32768^2)
+                const uint32_t prow = __umul24(y0 + r, pitch);
                 // lw >= 4: texel column cpos; lw = 2: columns 0 1 0 1 (pitch 4);
                 // lw = 1: texel 0 at positions 0 1 2 (pitch 3)
                 if (lw == 1 && cpos >= 3) continue;
                 const uint32_t col = lw >= 4 ? cpos : lw == 2 ? (cpos & 1u) : 0u;
                 const uint2 p0 = texel(lb, 4 * r + col), p1 = texel(lb + 1, 4 * r + col);
-                store_pair(row + kMaxTextures * (x0 + cpos), p0, p1);
+                store_pair(dst + (size_t)kMaxTextures * (prow + x0 + cpos), p0, p1);
                 if (lw >= 4 && x0 == 0 && cpos < 2)                        // wrap positions w, w + 1
-                    store_pair(row + kMaxTextures * (lw + cpos), p0, p1);
+                    store_pair(dst + (size_t)kMaxTextures * (prow + lw + cpos), p0, p1);
             }
         }
         return;
@@ -189,25 +188,25 @@ __device__ __forceinline__ void unpack_chunk(const UnpackSeg &sg, uint32_t chunk
             const uint32_t lb = (threadIdx.x & ~63u) + 32 * g + (lane >> 1);
             const uint32_t bj = first + lb;
             if (bj >= n_blk) continue;
-            const uint32_t x0 = 4 * (bj % bx), y0 = 4 * (bj / bx);
+            const uint32_t x0 = 4 * (bj & bxm), y0 = 4 * (bj >> bxs);
 #pragma unroll
             for (uint32_t r = 0; r < 4; ++r) {
                 if (y0 + r >= lh) break;          // a level shorter than 4 texels
                 const uint2 p0 = texel(lb, 4 * r + 2 * half), p1 = texel(lb, 4 * r + 2 * half + 1);
-                uint2 *row = dst + (size_t)(y0 + r) * pitch;
-                store_pair(row + x0 + 2 * half, p0, p1);
+                const uint32_t trow = __umul24(y0 + r, pitch);   // texel index, below 2^31
+                store_pair(dst + (trow + x0 + 2 * half), p0, p1);
                 if (x0 == 0 && half == 0)         // wrap columns w and w+1: texels 0 and 1
-                    store_pair(row + lw, p0, p1);
+                    store_pair(dst + (trow + lw), p0, p1);
             }
         }
     } else if (bi < n_blk) {
         // a level narrower than 4 texels keeps only the left part of its
         // blocks (and, shorter than 4, the top part)
-        const uint32_t y0 = 4 * (bi / bx);
+        const uint32_t y0 = 4 * (bi >> bxs);
 #pragma unroll
         for (uint32_t r = 0; r < 4; ++r) {
             if (y0 + r >= lh) break;
-            uint2 *row = dst + (size_t)(y0 + r) * pitch;
+            uint2 *row = dst + __umul24(y0 + r, pitch);
             const uint2 p0 = texel(threadIdx.x, 4 * r), p1 = texel(threadIdx.x, 4 * r + 1);
             if (lw == 2) {                        // pitch 4: texels 0 1 0 1
                 store_pair(row, p0, p1);

@@ -32,8 +32,14 @@ extern "C" void shim_decode_blocks_palette(const uint32_t *blocks, size_t n, int
             bcf::bc6h_header<false>(b[0], b[1], b[2], b[3], bcf::kTable, h);
             bcf::bc6h_palette<false>(h, pal);
         }
+        uint32_t s0, s1;
+        bcf::bc6h_slots(h, s0, s1);
         for (uint32_t t = 0; t < 16; ++t) {
-            const uint32_t j = bcf::bc6h_slot(h, t);
+            const uint32_t j = ((t < 8 ? s0 : s1) >> (4 * (t & 7))) & 15u;
+            if (j != bcf::bc6h_slot(h, t)) {
+                out[48 * i + 3 * t] = 0xDEADu;      // the packed slots disagree with the per-texel ones
+                continue;
+            }
             out[48 * i + 3 * t + 0] = (uint16_t)(pal[j][0] & 0xFFFFu);
             out[48 * i + 3 * t + 1] = (uint16_t)(pal[j][0] >> 16);
             out[48 * i + 3 * t + 2] = (uint16_t)pal[j][1];
