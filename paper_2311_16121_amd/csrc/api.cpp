@@ -242,13 +242,14 @@ size_t scratch_texels(const bcf::MaterialDesc &d)
     const bcf::TexDesc &T = d.tex[d.n_tex - 1];
     const uint32_t l = T.levels - 1;
     const size_t end = align_up(T.tex_off[l] + (size_t)scratch_pitch(level_dim(T.w, l)) * level_dim(T.h, l), 4);
-    return d.interleaved ? end * bcf::kMaxTextures : end;
+    return d.interleaved == bcf::kPacked ? end * 3 : d.interleaved ? end * bcf::kMaxTextures : end;
 }
 
 // Switch a material whose four pyramids share one geometry to the
-// position-interleaved scratch (MaterialDesc::interleaved); others keep the
+// position-interleaved scratch (MaterialDesc::interleaved = `mode`,
+// kInterleaved for a batch, kPacked for a single material); others keep the
 // per-pyramid layout.
-void interleave_if_shared(bcf::MaterialDesc &d)
+void interleave_if_shared(bcf::MaterialDesc &d, uint32_t mode = bcf::kInterleaved)
 {
     if (d.n_tex != (uint32_t)bcf::kMaxTextures) return;
     const bcf::TexDesc &A = d.tex[0];
@@ -262,10 +263,19 @@ void interleave_if_shared(bcf::MaterialDesc &d)
         off[l] = (uint32_t)pos;
         pos = align_up(pos + (size_t)scratch_pitch(level_dim(A.w, l)) * level_dim(A.h, l), 4);
     }
-    if (pos * bcf::kMaxTextures > kMaxScratchTexels) return;
+    if (pos * (mode == bcf::kPacked ? 3u : (uint32_t)bcf::kMaxTextures) > kMaxScratchTexels) return;
     for (uint32_t t = 0; t < d.n_tex; ++t)
         for (uint32_t l = 0; l < A.levels; ++l) d.tex[t].tex_off[l] = off[l];
-    d.interleaved = 1;
+    d.interleaved = mode;
+}
+
+// describe() for the single-material calls: four pyramids of one geometry
+// get the packed scratch.
+bcf_status describe_single(const bcf_material *m, bcf::MaterialDesc *d, bcf::MlpShape *sh)
+{
+    const bcf_status st = describe(m, d, sh);
+    if (st == BCF_OK) interleave_if_shared(*d, bcf::kPacked);
+    return st;
 }
 
 size_t elem_bytes(bcf::MlpKind k)
@@ -330,7 +340,7 @@ bcf::PredecodePlan predecode_plan(const bcf::MaterialDesc &d)
 bcf_status decode_args(const bcf_material *m, bcf_precision p, const void *ws, const float *queries, size_t n,
                        float *out, bcf::MaterialDesc *d, bcf::MlpShape *sh, bcf::MlpKind *kind)
 {
-    bcf_status st = describe(m, d, sh);
+    bcf_status st = describe_single(m, d, sh);
     if (st != BCF_OK) return st;
     if (!kind_of(p, kind)) return fail(BCF_ERR_UNSUPPORTED, "precision %d not supported", (int)p);
     if (n == 0) return BCF_OK;
@@ -546,7 +556,7 @@ bcf_status bcf_prepare(const bcf_material *m, bcf_precision p, void *ws, size_t 
 {
     bcf::MaterialDesc d;
     bcf::MlpShape sh;
-    bcf_status st = describe(m, &d, &sh);
+    bcf_status st = describe_single(m, &d, &sh);
     if (st != BCF_OK) return st;
     bcf::MlpKind kind;
     if (!kind_of(p, &kind)) return fail(BCF_ERR_UNSUPPORTED, "precision %d not supported", (int)p);
@@ -593,7 +603,7 @@ bcf_status bcf_unpack(const bcf_material *m, void *ws, void *stream)
 {
     bcf::MaterialDesc d;
     bcf::MlpShape sh;
-    bcf_status st = describe(m, &d, &sh);
+    bcf_status st = describe_single(m, &d, &sh);
     if (st != BCF_OK) return st;
     if (!ws || !aligned(ws, 256)) return fail(BCF_ERR_INVALID_ARG, "workspace NULL or not 256-byte aligned");
     // any precision: the scratch sits at the same offset in every precision's layout
@@ -630,7 +640,7 @@ bcf_status bcf_calibrate(const bcf_material *m, void *ws, const float *queries, 
 {
     bcf::MaterialDesc d;
     bcf::MlpShape sh;
-    bcf_status st = describe(m, &d, &sh);
+    bcf_status st = describe_single(m, &d, &sh);
     if (st != BCF_OK) return st;
     if (!ws || !aligned(ws, 256)) return fail(BCF_ERR_INVALID_ARG, "workspace NULL or not 256-byte aligned");
     if (!act_absmax || !aligned(act_absmax, 4)) return fail(BCF_ERR_INVALID_ARG, "act_absmax NULL or misaligned");
@@ -651,7 +661,7 @@ bcf_status bcf_decode_noalloc(const bcf_material *m, bcf_precision p, const floa
     bcf::MaterialDesc d;
     bcf::MlpShape sh;
     bcf::MlpKind kind;
-    bcf_status st = describe(m, &d, &sh);
+    bcf_status st = describe_single(m, &d, &sh);
     if (st != BCF_OK) return st;
     if (!kind_of(p, &kind)) return fail(BCF_ERR_UNSUPPORTED, "precision %d not supported", (int)p);
     if (n == 0) return BCF_OK;

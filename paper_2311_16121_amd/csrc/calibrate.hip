@@ -4,7 +4,7 @@
 
 namespace bcf {
 
-template <int C, bool SH>
+template <int C, int SH>
 static hipError_t launch_calib_c(const FrameArgs &a, const MlpShape &sh, unsigned grid, hipStream_t s)
 {
 #define BCF_CASE(H, NH)                                                                       \
@@ -19,11 +19,20 @@ static hipError_t launch_calib_c(const FrameArgs &a, const MlpShape &sh, unsigne
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_calibrate_kernel(const FrameArgs &a, const MlpShape &sh, bool shared, unsigned grid,
+template <int L>
+static hipError_t launch_calib_layout(const FrameArgs &a, const MlpShape &sh, unsigned grid, hipStream_t s)
+{
+    return sh.out <= 10 ? launch_calib_c<10, L>(a, sh, grid, s) : launch_calib_c<16, L>(a, sh, grid, s);
+}
+
+hipError_t launch_calibrate_kernel(const FrameArgs &a, const MlpShape &sh, int layout, unsigned grid,
                                    hipStream_t s)
 {
-    if (sh.out <= 10) return shared ? launch_calib_c<10, true>(a, sh, grid, s) : launch_calib_c<10, false>(a, sh, grid, s);
-    return shared ? launch_calib_c<16, true>(a, sh, grid, s) : launch_calib_c<16, false>(a, sh, grid, s);
+    switch (layout) {
+    case kLayoutPacked: return launch_calib_layout<kLayoutPacked>(a, sh, grid, s);
+    case kLayoutShared: return launch_calib_layout<kLayoutShared>(a, sh, grid, s);
+    default: return launch_calib_layout<kLayoutSplit>(a, sh, grid, s);
+    }
 }
 
 }  // namespace bcf

@@ -199,6 +199,61 @@ __device__ __forceinline__ void fetch4_interleaved(__amdgpu_buffer_rsrc_t rs, co
         }
 }
 
+// A query's trilinear footprint on a packed scratch (MaterialDesc::interleaved
+// = 2): position x of a level holds the four pyramids' (r, g, b) halves, 24
+// bytes, so a footprint row of all four is the 48 bytes of positions x0 and
+// x0 + 1, three 16-byte loads (a 32-byte position of 8-byte texels takes
+// four). q[level][row][k] = bytes 16k .. 16k + 15 of the row's span.
+struct PendingPacked {
+    Footprint f0, f1;
+    texel_pair q[2][2][3];
+};
+
+__device__ __forceinline__ void fetch4_packed(__amdgpu_buffer_rsrc_t rs, const LevelLut &lut,
+                                              const float *levels_bias, float u, float v, float s,
+                                              PendingPacked &p)
+{
+    const float uf = u - floorf(u), vf = v - floorf(v);       // wrap addressing
+    const LevelSel ls = select_levels(s, levels_bias[1], __builtin_bit_cast(uint32_t, levels_bias[0]));
+    p.f0 = footprint<24>(lut.e[0][ls.l0], uf, vf, 1.0f - ls.lam);
+    p.f1 = footprint<24>(lut.e[0][ls.l1], uf, vf, ls.lam);
+    const uint32_t off[2][2] = {{p.f0.o0, p.f0.o1}, {p.f1.o0, p.f1.o1}};
+#pragma unroll
+    for (int lv = 0; lv < 2; ++lv)
+#pragma unroll
+        for (int row = 0; row < 2; ++row)
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                p.q[lv][row][k] = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(off[lv][row] + 16u * k), 0, 0);
+}
+
+// Half h (0..23) of a packed footprint row: position h / 12, pyramid
+// (h % 12) / 3, channel h % 3.
+__device__ __forceinline__ float packed_half(const texel_pair (&q)[3], int h)
+{
+    const uint32_t d = q[h >> 3][(h >> 1) & 3];
+    return (h & 1) ? half_hi(d) : half_lo(d);
+}
+
+// filter_pending for packed taps: the same sums in the same order (per
+// pyramid and channel: level l0's four taps, then level l1's).
+__device__ __forceinline__ void filter_pending_packed(const PendingPacked &p, float z[12])
+{
+#pragma unroll
+    for (int i = 0; i < 12; ++i) z[i] = 0.0f;
+#pragma unroll
+    for (int lv = 0; lv < 2; ++lv) {
+        const Footprint &f = lv ? p.f1 : p.f0;
+#pragma unroll
+        for (int i = 0; i < 12; ++i) {           // i = 3 t + c: halves i (x0) and 12 + i (x0 + 1)
+            z[i] = fmaf(f.w00, packed_half(p.q[lv][0], i), z[i]);
+            z[i] = fmaf(f.w10, packed_half(p.q[lv][0], 12 + i), z[i]);
+            z[i] = fmaf(f.w01, packed_half(p.q[lv][1], i), z[i]);
+            z[i] = fmaf(f.w11, packed_half(p.q[lv][1], 12 + i), z[i]);
+        }
+    }
+}
+
 // the sums of filter4<true> from fetched taps
 __device__ __forceinline__ void filter_pending(const PendingTaps &p, float z[12])
 {
@@ -211,19 +266,31 @@ __device__ __forceinline__ void filter_pending(const PendingTaps &p, float z[12]
     }
 }
 
+// Scratch layouts of a single material's decode: each pyramid's own levels
+// (kLayoutSplit), the same with one shared geometry, slot t t * stride bytes
+// after slot 0 (kLayoutShared), or four pyramids of one geometry packed per
+// position (kLayoutPacked).
+constexpr int kLayoutSplit = 0, kLayoutShared = 1, kLayoutPacked = 2;
+
 // z[3t + c] = T_t(u, v, s) channel c for the four pyramid slots (slots past
 // the material's pyramids repeat slot 0; their MLP weights are zero).
-// SHARED: every slot has the same w, h, levels and bias and slot t starts
-// t * stride bytes after slot 0, so one footprint serves all four.
-template <bool SHARED>
+// kLayoutShared / kLayoutPacked: every slot has the same w, h, levels and
+// bias, so one footprint serves all four.
+template <int LAYOUT>
 __device__ __forceinline__ void filter4(__amdgpu_buffer_rsrc_t rs, const LevelLut &lut,
                                         const float *levels_bias, uint32_t stride, float u, float v,
                                         float s, float z[12])
 {
+    if (LAYOUT == kLayoutPacked) {
+        PendingPacked p;
+        fetch4_packed(rs, lut, levels_bias, u, v, s, p);
+        filter_pending_packed(p, z);
+        return;
+    }
     const float uf = u - floorf(u), vf = v - floorf(v);       // wrap addressing
 #pragma unroll
     for (int i = 0; i < 12; ++i) z[i] = 0.0f;
-    if (SHARED) {
+    if (LAYOUT == kLayoutShared) {
         const LevelSel ls = select_levels(s, levels_bias[1], __builtin_bit_cast(uint32_t, levels_bias[0]));
         const Footprint f0 = footprint(lut.e[0][ls.l0], uf, vf, 1.0f - ls.lam);
         const Footprint f1 = footprint(lut.e[0][ls.l1], uf, vf, ls.lam);

@@ -3,10 +3,13 @@
 
 namespace bcf {
 
-hipError_t launch_frame_fp8(const FrameArgs &a, const MlpShape &sh, bool shared, hipStream_t s)
+hipError_t launch_frame_fp8(const FrameArgs &a, const MlpShape &sh, int layout, hipStream_t s)
 {
-    return shared ? launch_frame_kind<MLP_MFMA_FP8, 16, true>(a, sh, s)
-                  : launch_frame_kind<MLP_MFMA_FP8, 16, false>(a, sh, s);
+    switch (layout) {
+    case kLayoutPacked: return launch_frame_kind<MLP_MFMA_FP8, 16, kLayoutPacked>(a, sh, s);
+    case kLayoutShared: return launch_frame_kind<MLP_MFMA_FP8, 16, kLayoutShared>(a, sh, s);
+    default: return launch_frame_kind<MLP_MFMA_FP8, 16, kLayoutSplit>(a, sh, s);
+    }
 }
 
 }  // namespace bcf

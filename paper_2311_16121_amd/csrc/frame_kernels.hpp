@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <type_traits>
 
 #include "filter_device.hpp"
 #include "internal.hpp"
@@ -239,7 +240,7 @@ __device__ __forceinline__ void mlp_stage(const float z[12], const uint8_t *wbas
 }
 
 // One wave's 64 queries: filter (eqs. 9, 10), concatenate, MLP.
-template <MlpKind K, int H, int NH, int C, bool SHARED>
+template <MlpKind K, int H, int NH, int C, int LAYOUT>
 __device__ __forceinline__ void decode_wave(const Query &qq, __amdgpu_buffer_rsrc_t rs, const LevelLut &lut,
                                             const float *levels_bias, uint32_t stride, const uint8_t *wbase,
                                             const WsLayout &lay,
@@ -247,7 +248,7 @@ __device__ __forceinline__ void decode_wave(const Query &qq, __amdgpu_buffer_rsr
                                             float4_t (*feats)[4], float *st, uint32_t out_dim, uint32_t lane)
 {
     float z[12];
-    filter4<SHARED>(rs, lut, levels_bias, stride, qq.u, qq.v, qq.s, z);
+    filter4<LAYOUT>(rs, lut, levels_bias, stride, qq.u, qq.v, qq.s, z);
     mlp_stage<K, H, NH, C>(z, wbase, lay, mlp, feats, st, out_dim, lane);
 }
 
@@ -352,7 +353,7 @@ struct Width {
     static constexpr int value = V;
 };
 
-template <MlpKind K, int H, int NH, int C, bool SHARED>
+template <MlpKind K, int H, int NH, int C, int LAYOUT>
 __global__ void __launch_bounds__(kFrameThreads) k_frame(FrameArgs a)
 {
     constexpr bool VALU = K == MLP_VALU_F32;
@@ -405,7 +406,7 @@ __global__ void __launch_bounds__(kFrameThreads) k_frame(FrameArgs a)
     auto run = [&](auto width) {
         constexpr int V = decltype(width)::value;
         uint32_t it, row0, col0, i_, r_, c_;
-        if (SHARED) {
+        if (LAYOUT != kLayoutSplit) {
             // Per item: blend its texels, run the MLP, issue the next item's
             // texel loads and the query after that, then store -- so the
             // wait for the next texels never includes these stores. The loop
@@ -413,18 +414,24 @@ __global__ void __launch_bounds__(kFrameThreads) k_frame(FrameArgs a)
             // stores), and the last item fetches its first item again, so
             // every path into the loop's top has the same loads and stores
             // outstanding.
+            using Taps = std::conditional_t<LAYOUT == kLayoutPacked, PendingPacked, PendingTaps>;
+            auto fetch = [&](const Query &q, Taps &t) {
+                if constexpr (LAYOUT == kLayoutPacked) fetch4_packed(rs, lut, a.levels_bias, q.u, q.v, q.s, t);
+                else fetch4_shared(rs, lut, a.levels_bias, a.stride, q.u, q.v, q.s, t);
+            };
             auto clamp_item = [&](uint32_t k) { return k < items.end ? k : items.first; };
             const Query q0 = load_query(rq, query_of(items.first, i_, r_, c_));
-            PendingTaps taps;
-            fetch4_shared(rs, lut, a.levels_bias, a.stride, q0.u, q0.v, q0.s, taps);
+            Taps taps;
+            fetch(q0, taps);
             Query qnext = load_query(rq, query_of(clamp_item(items.first + items.step), i_, r_, c_));
             store_dummies<V>(ro, oob);
             for (uint32_t k = items.first; k < items.end; k += items.step) {
                 query_of(k, it, row0, col0);
                 float z[12];
-                filter_pending(taps, z);
+                if constexpr (LAYOUT == kLayoutPacked) filter_pending_packed(taps, z);
+                else filter_pending(taps, z);
                 mlp_stage<K, H, NH, C>(z, a.ws, a.lay, mlp, feats, st, a.out_dim, lane);
-                fetch4_shared(rs, lut, a.levels_bias, a.stride, qnext.u, qnext.v, qnext.s, taps);
+                fetch(qnext, taps);
                 qnext = load_query(rq, query_of(clamp_item(k + 2 * items.step), i_, r_, c_));
                 store_item<V>(a, oob, st, ro, it, row0, col0, lane);
                 wave_lds_sync();
@@ -436,7 +443,7 @@ __global__ void __launch_bounds__(kFrameThreads) k_frame(FrameArgs a)
                 query_of(k, it, row0, col0);
                 const Query qq = next;
                 if (k + items.step < items.end) next = load_query(rq, query_of(k + items.step, i_, r_, c_));
-                decode_wave<K, H, NH, C, SHARED>(qq, rs, lut, a.levels_bias, a.stride, a.ws, a.lay, mlp, feats,
+                decode_wave<K, H, NH, C, kLayoutSplit>(qq, rs, lut, a.levels_bias, a.stride, a.ws, a.lay, mlp, feats,
                                                  st, a.out_dim, lane);
                 store_item<V>(a, oob, st, ro, it, row0, col0, lane);
                 wave_lds_sync();
@@ -451,7 +458,7 @@ __global__ void __launch_bounds__(kFrameThreads) k_frame(FrameArgs a)
 
 // The plain fp32 decode that records each layer's largest input magnitude
 // (the static fp8 activation scales come from a calibration batch).
-template <int H, int NH, int C, bool SHARED>
+template <int H, int NH, int C, int LAYOUT>
 __global__ void __launch_bounds__(kFrameThreads) k_calibrate(FrameArgs a)
 {
     __shared__ LevelLut lut;
@@ -464,7 +471,7 @@ __global__ void __launch_bounds__(kFrameThreads) k_calibrate(FrameArgs a)
     for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < a.n; q += gridDim.x * blockDim.x) {
         const Query qq = load_query(rq, q);
         float z[12], o[C];
-        filter4<SHARED>(rs, lut, a.levels_bias, a.stride, qq.u, qq.v, qq.s, z);
+        filter4<LAYOUT>(rs, lut, a.levels_bias, a.stride, qq.u, qq.v, qq.s, z);
         mlp_valu<H, NH, C>(a.ws, a.lay, z, o, amax);
     }
 #pragma unroll
@@ -595,10 +602,10 @@ __global__ void __launch_bounds__(64 * W) k_batch(BatchArgs a)
             decode_wave_interleaved<K, H, NH, C>(qq, rs, lut[wv], lb, wbase, a.lay, mlp, feats, st, a.out_dim,
                                                  lane);
         else if (shared)
-            decode_wave<K, H, NH, C, true>(qq, rs, lut[wv], lb, stride, wbase, a.lay, mlp, feats, st,
+            decode_wave<K, H, NH, C, kLayoutShared>(qq, rs, lut[wv], lb, stride, wbase, a.lay, mlp, feats, st,
                                            a.out_dim, lane);
         else
-            decode_wave<K, H, NH, C, false>(qq, rs, lut[wv], lb, stride, wbase, a.lay, mlp, feats, st,
+            decode_wave<K, H, NH, C, kLayoutSplit>(qq, rs, lut[wv], lb, stride, wbase, a.lay, mlp, feats, st,
                                             a.out_dim, lane);
         store_run(stage[wv], ro, j, n_k, a.out_dim, lane);
         wave_lds_sync();
@@ -656,7 +663,7 @@ inline unsigned frame_launch_grid(uint32_t n_items, unsigned cap)
     return std::min(std::max(kXcds, (want + kXcds - 1) / kXcds * kXcds), cap);
 }
 
-template <MlpKind K, int C, bool SH>
+template <MlpKind K, int C, int SH>
 hipError_t launch_frame_kind(const FrameArgs &a, const MlpShape &sh, hipStream_t s)
 {
     constexpr unsigned kOversub = K == MLP_VALU_F32 ? 4 : 2;
@@ -675,12 +682,13 @@ hipError_t launch_frame_kind(const FrameArgs &a, const MlpShape &sh, hipStream_t
 }
 
 // per-precision entry points (frame_<precision>.hip)
-hipError_t launch_frame_f32(const FrameArgs &a, const MlpShape &sh, bool shared, hipStream_t s);
-hipError_t launch_frame_f16(const FrameArgs &a, const MlpShape &sh, bool shared, hipStream_t s);
-hipError_t launch_frame_bf16(const FrameArgs &a, const MlpShape &sh, bool shared, hipStream_t s);
-hipError_t launch_frame_fp8(const FrameArgs &a, const MlpShape &sh, bool shared, hipStream_t s);
-hipError_t launch_frame_f32_mfma(const FrameArgs &a, const MlpShape &sh, bool shared, hipStream_t s);
-hipError_t launch_calibrate_kernel(const FrameArgs &a, const MlpShape &sh, bool shared, unsigned grid,
+// layout: kLayoutSplit, kLayoutShared or kLayoutPacked (filter_device.hpp)
+hipError_t launch_frame_f32(const FrameArgs &a, const MlpShape &sh, int layout, hipStream_t s);
+hipError_t launch_frame_f16(const FrameArgs &a, const MlpShape &sh, int layout, hipStream_t s);
+hipError_t launch_frame_bf16(const FrameArgs &a, const MlpShape &sh, int layout, hipStream_t s);
+hipError_t launch_frame_fp8(const FrameArgs &a, const MlpShape &sh, int layout, hipStream_t s);
+hipError_t launch_frame_f32_mfma(const FrameArgs &a, const MlpShape &sh, int layout, hipStream_t s);
+hipError_t launch_calibrate_kernel(const FrameArgs &a, const MlpShape &sh, int layout, unsigned grid,
                                    hipStream_t s);
 hipError_t launch_batch_f16(const BatchArgs &a, const MlpShape &sh, unsigned grid, uint32_t waves, hipStream_t s);
 hipError_t launch_batch_f32(const BatchArgs &a, const MlpShape &sh, unsigned grid, uint32_t waves, hipStream_t s);

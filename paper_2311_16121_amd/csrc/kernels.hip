@@ -97,6 +97,17 @@ __device__ __forceinline__ void store_pair(uint2 *dst, uint2 t0, uint2 t1)
     __builtin_nontemporal_store((u32x4_t){t0.x, t0.y, t1.x, t1.y}, (global_u32x4 *)dst);
 }
 
+typedef uint32_t u32x3_t __attribute__((ext_vector_type(3)));
+typedef __attribute__((address_space(1))) u32x3_t global_u32x3;
+
+// Two pyramids' texels of one position of a packed scratch, (r, g, b) halves
+// each, as one 12-byte non-temporal store (dst 4-byte aligned).
+__device__ __forceinline__ void store_packed_pair(uint32_t *dst, uint2 t0, uint2 t1)
+{
+    const u32x3_t v = {t0.x, (t0.y & 0xFFFFu) | (t1.x << 16), (t1.x >> 16) | (t1.y << 16)};
+    __builtin_nontemporal_store(v, (global_u32x3 *)dst);
+}
+
 // One chunk (256 lanes) of one unpack segment into the texel scratch. The
 // whole workgroup calls it (it synchronises once); `palette` and `slots` are
 // the workgroup's LDS, `table` the mode table. With `list` (LDS, interleaved
@@ -149,6 +160,9 @@ __device__ __forceinline__ void unpack_chunk(const UnpackSeg &sg, uint32_t chunk
         // (position L % 8 / 2 of the row, pyramids 2(L%2) and 2(L%2)+1) of
         // block 8h + L / 8, read through LDS from that block's lanes.
         // Non-temporal like the per-pyramid layout's stores.
+        // packed: 24-byte positions, lane L's two pyramids 12 bytes of them
+        const bool packed = (sg.flags & kSegPacked) != 0;
+        uint32_t *pdst = reinterpret_cast<uint32_t *>(sg.texels);
         const uint32_t lane = threadIdx.x & 63u, wave0 = threadIdx.x & ~63u;
         const uint32_t chunk8 = lane & 7u, pp = 2 * (lane & 1u), cpos = chunk8 >> 1;
         for (uint32_t h = 0; h < 2; ++h) {
@@ -168,9 +182,14 @@ __device__ __forceinline__ void unpack_chunk(const UnpackSeg &sg, uint32_t chunk
                 if (lw == 1 && cpos >= 3) continue;
                 const uint32_t col = lw >= 4 ? cpos : lw == 2 ? (cpos & 1u) : 0u;
                 const uint2 p0 = texel(lb, 4 * r + col), p1 = texel(lb + 1, 4 * r + col);
-                store_pair(dst + (size_t)kMaxTextures * (prow + x0 + cpos), p0, p1);
-                if (lw >= 4 && x0 == 0 && cpos < 2)                        // wrap positions w, w + 1
-                    store_pair(dst + (size_t)kMaxTextures * (prow + lw + cpos), p0, p1);
+                const bool wrap = lw >= 4 && x0 == 0 && cpos < 2;           // also positions w, w + 1
+                if (packed) {
+                    store_packed_pair(pdst + 6 * (size_t)(prow + x0 + cpos) + 3 * (pp >> 1), p0, p1);
+                    if (wrap) store_packed_pair(pdst + 6 * (size_t)(prow + lw + cpos) + 3 * (pp >> 1), p0, p1);
+                } else {
+                    store_pair(dst + (size_t)kMaxTextures * (prow + x0 + cpos), p0, p1);
+                    if (wrap) store_pair(dst + (size_t)kMaxTextures * (prow + lw + cpos), p0, p1);
+                }
             }
         }
         return;
@@ -236,9 +255,11 @@ __device__ __forceinline__ UnpackSeg material_seg(const PredecodeArgs &a, uint32
     const TexDesc &T0 = a.m.tex[il ? 0u : a.p.seg_tex[seg]];
     sg.lw = max(T0.w >> l, 1u);
     sg.lh = max(T0.h >> l, 1u);
-    sg.texels = a.texels + (il ? (size_t)kMaxTextures : 1u) * T0.tex_off[l];
+    // 8-byte units per position: 4 interleaved, 3 packed, 1 per pyramid
+    const size_t unit = il == kPacked ? 3u : il ? (size_t)kMaxTextures : 1u;
+    sg.texels = a.texels + unit * T0.tex_off[l];
     sg.wg0 = a.p.seg_wg[seg];
-    sg.flags = il ? kSegInterleaved : 0u;
+    sg.flags = il ? (kSegInterleaved | (il == kPacked ? kSegPacked : 0u)) : 0u;
     return sg;
 }
 
@@ -541,8 +562,10 @@ __global__ void k_fill(float *p, uint32_t n, float v)
 }
 
 // Frame arguments common to the decode and the calibration.
+// *layout: kLayoutPacked for a packed scratch, kLayoutShared for pyramids of
+// one geometry a constant stride apart, else kLayoutSplit.
 static FrameArgs frame_args(const MaterialDesc &m, const WsLayout &lay, const void *ws, uint32_t out_dim,
-                            bool *shared)
+                            int *layout)
 {
     FrameArgs a;
     std::memset(&a, 0, sizeof a);
@@ -564,14 +587,15 @@ static FrameArgs frame_args(const MaterialDesc &m, const WsLayout &lay, const vo
         a.levels_bias[2 * t + 1] = T.bias;
     }
     // shared geometry: identical w, h, levels and bias, scratch a constant stride apart
-    *shared = true;
+    bool shared = true;
     const uint32_t stride_texels = m.n_tex > 1 ? m.tex[1].tex_off[0] - m.tex[0].tex_off[0] : 0;
     for (uint32_t t = 1; t < m.n_tex; ++t) {
         const TexDesc &A = m.tex[0], &B = m.tex[t];
-        if (A.w != B.w || A.h != B.h || A.levels != B.levels || A.bias != B.bias) *shared = false;
-        for (uint32_t l = 0; l < A.levels && *shared; ++l)
-            if (B.tex_off[l] != A.tex_off[l] + t * stride_texels) *shared = false;
+        if (A.w != B.w || A.h != B.h || A.levels != B.levels || A.bias != B.bias) shared = false;
+        for (uint32_t l = 0; l < A.levels && shared; ++l)
+            if (B.tex_off[l] != A.tex_off[l] + t * stride_texels) shared = false;
     }
+    *layout = m.interleaved == kPacked ? kLayoutPacked : shared ? kLayoutShared : kLayoutSplit;
     a.stride = stride_texels * 8u;
     a.ws = static_cast<const uint8_t *>(ws);
     a.lay = lay;
@@ -593,15 +617,15 @@ hipError_t launch_filter_mlp(const MaterialDesc &m, const MlpShape &sh, MlpKind 
                              const WsLayout &lay, const void *ws, const float *queries, size_t n,
                              uint32_t grid_width, float *out, hipStream_t s)
 {
-    bool shared;
-    FrameArgs a = frame_args(m, lay, ws, sh.out, &shared);
+    int layout;
+    FrameArgs a = frame_args(m, lay, ws, sh.out, &layout);
     auto launch = [&]() -> hipError_t {
         switch (kind) {
-        case MLP_VALU_F32: return launch_frame_f32(a, sh, shared, s);
-        case MLP_MFMA_F16: return launch_frame_f16(a, sh, shared, s);
-        case MLP_MFMA_BF16: return launch_frame_bf16(a, sh, shared, s);
-        case MLP_MFMA_FP8: return launch_frame_fp8(a, sh, shared, s);
-        case MLP_MFMA_F32: return launch_frame_f32_mfma(a, sh, shared, s);
+        case MLP_VALU_F32: return launch_frame_f32(a, sh, layout, s);
+        case MLP_MFMA_F16: return launch_frame_f16(a, sh, layout, s);
+        case MLP_MFMA_BF16: return launch_frame_bf16(a, sh, layout, s);
+        case MLP_MFMA_FP8: return launch_frame_fp8(a, sh, layout, s);
+        case MLP_MFMA_F32: return launch_frame_f32_mfma(a, sh, layout, s);
         default: return hipErrorInvalidValue;
         }
     };
@@ -801,8 +825,8 @@ hipError_t write_batch_table(const MaterialDesc *mats, const BatchSlot *slots, u
         WsLayout lay;
         std::memset(&lay, 0, sizeof lay);
         lay.scratch_off = slots[k].scratch_off;
-        bool shared;
-        const FrameArgs a = frame_args(mats[k], lay, ws, out_dim, &shared);
+        int layout;
+        const FrameArgs a = frame_args(mats[k], lay, ws, out_dim, &layout);
         BatchMat &b = table[k];
         std::memset(&b, 0, sizeof b);
         b.lut = a.lut;
@@ -811,7 +835,7 @@ hipError_t write_batch_table(const MaterialDesc *mats, const BatchSlot *slots, u
         b.weights_off = slots[k].weights_off;
         b.scratch_bytes = (uint32_t)slots[k].scratch_bytes;
         b.stride = a.stride;
-        b.shared = shared ? 1u : 0u;
+        b.shared = layout != kLayoutSplit ? 1u : 0u;
         b.interleaved = mats[k].interleaved;
         std::memcpy(b.seg_chunk, slots[k].seg_chunk, sizeof b.seg_chunk);
     }
@@ -857,15 +881,15 @@ hipError_t launch_calibrate(const MaterialDesc &m, const MlpShape &sh, const WsL
     k_fill<<<1, 64, 0, s>>>(absmax, sh.n_hidden + 1, 0.0f);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    bool shared;
-    FrameArgs a = frame_args(m, lay, ws, sh.out, &shared);
+    int layout;
+    FrameArgs a = frame_args(m, lay, ws, sh.out, &layout);
     a.absmax = absmax;
     for (size_t first = 0; first < n; first += kMaxQueriesPerLaunch) {
         const uint32_t cnt = (uint32_t)std::min<size_t>(n - first, kMaxQueriesPerLaunch);
         a.queries = queries + 3 * first;
         a.n = cnt;
         const unsigned grid = std::max(1u, std::min<uint32_t>((cnt + kFrameThreads - 1) / kFrameThreads, 1024u));
-        e = launch_calibrate_kernel(a, sh, shared, grid, s);
+        e = launch_calibrate_kernel(a, sh, layout, grid, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
