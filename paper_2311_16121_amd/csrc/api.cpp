@@ -500,7 +500,7 @@ bcf_status describe_batch(const bcf_material *mats, uint32_t n_mats, bcf_precisi
                    std::memcmp(sh.dims, b->sh.dims, sizeof(uint32_t) * (sh.n_layers + 1)) != 0) {
             return fail(BCF_ERR_INVALID_ARG, "material %u: MLP dims differ from material 0", k);
         }
-        interleave_if_shared(b->descs[k]);
+        interleave_if_shared(b->descs[k], bcf::kPacked);
         const bcf::PredecodePlan plan = predecode_plan(b->descs[k]);
         b->n_seg += plan.n_seg;
         b->n_chunks += plan.seg_wg[plan.n_seg];
@@ -795,11 +795,14 @@ bcf_status bcf_prepare_batch(const bcf_material *mats, uint32_t n_mats, bcf_prec
                 const bcf::TexDesc &T = d.interleaved ? d.tex[t < d.n_tex ? t : 0u] : T0;
                 g.blocks[t] = T.blocks + T.blk_off[l];
             }
-            g.texels = texels + (d.interleaved ? (size_t)bcf::kMaxTextures : 1u) * T0.tex_off[l];
+            // 8-byte units per position: 3 packed, 4 interleaved, 1 per pyramid
+            g.texels = texels + (d.interleaved == bcf::kPacked ? 3u : d.interleaved ? (size_t)bcf::kMaxTextures : 1u) *
+                                    T0.tex_off[l];
             g.lw = level_dim(T0.w, l);
             g.lh = level_dim(T0.h, l);
             g.wg0 = chunk0 + plan.seg_wg[j];
-            g.flags = (d.interleaved ? bcf::kSegInterleaved : 0u) | (d.is_signed ? bcf::kSegSigned : 0u);
+            g.flags = (d.interleaved ? bcf::kSegInterleaved : 0u) | (d.interleaved == bcf::kPacked ? bcf::kSegPacked : 0u) |
+                      (d.is_signed ? bcf::kSegSigned : 0u);
             const uint32_t end = chunk0 + plan.seg_wg[j + 1];
             std::fill(chunk_seg.begin() + g.wg0, chunk_seg.begin() + end, (uint32_t)segs.size());
             for (uint32_t c = g.wg0; c < end; c += d.interleaved ? 4u : 1u) units.push_back(c);

@@ -261,10 +261,10 @@ __device__ __forceinline__ void decode_wave_interleaved(const Query &qq, __amdgp
                                                         float4_t (*feats)[4], float *st, uint32_t out_dim,
                                                         uint32_t lane)
 {
-    PendingTaps taps;
-    fetch4_interleaved(rs, lut, levels_bias, qq.u, qq.v, qq.s, taps);
+    PendingPacked taps;
+    fetch4_packed(rs, lut, levels_bias, qq.u, qq.v, qq.s, taps);
     float z[12];
-    filter_pending(taps, z);
+    filter_pending_packed(taps, z);
     mlp_stage<K, H, NH, C>(z, wbase, lay, mlp, feats, st, out_dim, lane);
 }
 
