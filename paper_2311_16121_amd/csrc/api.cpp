@@ -242,14 +242,13 @@ size_t scratch_texels(const bcf::MaterialDesc &d)
     const bcf::TexDesc &T = d.tex[d.n_tex - 1];
     const uint32_t l = T.levels - 1;
     const size_t end = align_up(T.tex_off[l] + (size_t)scratch_pitch(level_dim(T.w, l)) * level_dim(T.h, l), 4);
-    return d.interleaved == bcf::kPacked ? end * 3 : d.interleaved ? end * bcf::kMaxTextures : end;
+    return d.interleaved ? end * 3 : end;          // a packed position is three 8-byte units
 }
 
 // Switch a material whose four pyramids share one geometry to the
-// position-interleaved scratch (MaterialDesc::interleaved = `mode`,
-// kInterleaved for a batch, kPacked for a single material); others keep the
+// position-packed scratch (MaterialDesc::interleaved); others keep the
 // per-pyramid layout.
-void interleave_if_shared(bcf::MaterialDesc &d, uint32_t mode = bcf::kInterleaved)
+void interleave_if_shared(bcf::MaterialDesc &d)
 {
     if (d.n_tex != (uint32_t)bcf::kMaxTextures) return;
     const bcf::TexDesc &A = d.tex[0];
@@ -263,10 +262,10 @@ void interleave_if_shared(bcf::MaterialDesc &d, uint32_t mode = bcf::kInterleave
         off[l] = (uint32_t)pos;
         pos = align_up(pos + (size_t)scratch_pitch(level_dim(A.w, l)) * level_dim(A.h, l), 4);
     }
-    if (pos * (mode == bcf::kPacked ? 3u : (uint32_t)bcf::kMaxTextures) > kMaxScratchTexels) return;
+    if (pos * 3 > kMaxScratchTexels) return;
     for (uint32_t t = 0; t < d.n_tex; ++t)
         for (uint32_t l = 0; l < A.levels; ++l) d.tex[t].tex_off[l] = off[l];
-    d.interleaved = mode;
+    d.interleaved = 1;
 }
 
 // describe() for the single-material calls: four pyramids of one geometry
@@ -274,7 +273,7 @@ void interleave_if_shared(bcf::MaterialDesc &d, uint32_t mode = bcf::kInterleave
 bcf_status describe_single(const bcf_material *m, bcf::MaterialDesc *d, bcf::MlpShape *sh)
 {
     const bcf_status st = describe(m, d, sh);
-    if (st == BCF_OK) interleave_if_shared(*d, bcf::kPacked);
+    if (st == BCF_OK) interleave_if_shared(*d);
     return st;
 }
 
@@ -500,7 +499,7 @@ bcf_status describe_batch(const bcf_material *mats, uint32_t n_mats, bcf_precisi
                    std::memcmp(sh.dims, b->sh.dims, sizeof(uint32_t) * (sh.n_layers + 1)) != 0) {
             return fail(BCF_ERR_INVALID_ARG, "material %u: MLP dims differ from material 0", k);
         }
-        interleave_if_shared(b->descs[k], bcf::kPacked);
+        interleave_if_shared(b->descs[k]);
         const bcf::PredecodePlan plan = predecode_plan(b->descs[k]);
         b->n_seg += plan.n_seg;
         b->n_chunks += plan.seg_wg[plan.n_seg];
@@ -795,14 +794,12 @@ bcf_status bcf_prepare_batch(const bcf_material *mats, uint32_t n_mats, bcf_prec
                 const bcf::TexDesc &T = d.interleaved ? d.tex[t < d.n_tex ? t : 0u] : T0;
                 g.blocks[t] = T.blocks + T.blk_off[l];
             }
-            // 8-byte units per position: 3 packed, 4 interleaved, 1 per pyramid
-            g.texels = texels + (d.interleaved == bcf::kPacked ? 3u : d.interleaved ? (size_t)bcf::kMaxTextures : 1u) *
-                                    T0.tex_off[l];
+            // 8-byte units per position: 3 packed, 1 per pyramid
+            g.texels = texels + (d.interleaved ? 3u : 1u) * (size_t)T0.tex_off[l];
             g.lw = level_dim(T0.w, l);
             g.lh = level_dim(T0.h, l);
             g.wg0 = chunk0 + plan.seg_wg[j];
-            g.flags = (d.interleaved ? bcf::kSegInterleaved : 0u) | (d.interleaved == bcf::kPacked ? bcf::kSegPacked : 0u) |
-                      (d.is_signed ? bcf::kSegSigned : 0u);
+            g.flags = (d.interleaved ? bcf::kSegInterleaved : 0u) | (d.is_signed ? bcf::kSegSigned : 0u);
             const uint32_t end = chunk0 + plan.seg_wg[j + 1];
             std::fill(chunk_seg.begin() + g.wg0, chunk_seg.begin() + end, (uint32_t)segs.size());
             for (uint32_t c = g.wg0; c < end; c += d.interleaved ? 4u : 1u) units.push_back(c);

@@ -90,8 +90,8 @@ __device__ __forceinline__ TapCoords tap_coords(uint4 e, float uf, float vf)
     return t;
 }
 
-// UNIT: bytes per texel slot of the scratch (8; 32 for an interleaved one,
-// whose LUT offsets count 32-byte positions)
+// UNIT: bytes per texel slot of the scratch (8; 24 for a packed one, whose
+// LUT offsets count 24-byte positions)
 template <uint32_t UNIT = 8>
 __device__ __forceinline__ Footprint footprint(uint4 e, float uf, float vf, float lw)
 {
@@ -170,40 +170,10 @@ __device__ __forceinline__ void fetch4_shared(__amdgpu_buffer_rsrc_t rs, const L
     }
 }
 
-// fetch4_shared for a position-interleaved scratch (MaterialDesc::interleaved):
-// a footprint row of all four pyramids is the 64 bytes of positions x0 and
-// x0 + 1, four 16-byte loads, regrouped into each pyramid's texel pair.
-__device__ __forceinline__ void fetch4_interleaved(__amdgpu_buffer_rsrc_t rs, const LevelLut &lut,
-                                                   const float *levels_bias, float u, float v, float s,
-                                                   PendingTaps &p)
-{
-    const float uf = u - floorf(u), vf = v - floorf(v);       // wrap addressing
-    const LevelSel ls = select_levels(s, levels_bias[1], __builtin_bit_cast(uint32_t, levels_bias[0]));
-    p.f0 = footprint<32>(lut.e[0][ls.l0], uf, vf, 1.0f - ls.lam);
-    p.f1 = footprint<32>(lut.e[0][ls.l1], uf, vf, ls.lam);
-    const uint32_t off[2][2] = {{p.f0.o0, p.f0.o1}, {p.f1.o0, p.f1.o1}};
-#pragma unroll
-    for (int lv = 0; lv < 2; ++lv)
-#pragma unroll
-        for (int row = 0; row < 2; ++row) {
-            const uint32_t o = off[lv][row];
-            // position x0: pyramids 0, 1 | 2, 3; position x0 + 1: the same
-            const texel_pair a01 = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)o, 0, 0);
-            const texel_pair a23 = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(o + 16u), 0, 0);
-            const texel_pair b01 = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(o + 32u), 0, 0);
-            const texel_pair b23 = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(o + 48u), 0, 0);
-            p.r[0][lv][row] = texel_pair{a01[0], a01[1], b01[0], b01[1]};
-            p.r[1][lv][row] = texel_pair{a01[2], a01[3], b01[2], b01[3]};
-            p.r[2][lv][row] = texel_pair{a23[0], a23[1], b23[0], b23[1]};
-            p.r[3][lv][row] = texel_pair{a23[2], a23[3], b23[2], b23[3]};
-        }
-}
-
-// A query's trilinear footprint on a packed scratch (MaterialDesc::interleaved
-// = 2): position x of a level holds the four pyramids' (r, g, b) halves, 24
-// bytes, so a footprint row of all four is the 48 bytes of positions x0 and
-// x0 + 1, three 16-byte loads (a 32-byte position of 8-byte texels takes
-// four). q[level][row][k] = bytes 16k .. 16k + 15 of the row's span.
+// A query's trilinear footprint on a packed scratch (MaterialDesc::interleaved):
+// position x of a level holds the four pyramids' (r, g, b) halves, 24 bytes,
+// so a footprint row of all four is the 48 bytes of positions x0 and x0 + 1,
+// three 16-byte loads (four 8-byte texels per position would take four). q[level][row][k] = bytes 16k .. 16k + 15 of the row's span.
 struct PendingPacked {
     Footprint f0, f1;
     texel_pair q[2][2][3];

@@ -28,18 +28,14 @@ struct MaterialDesc {
     TexDesc tex[kMaxTextures];
     uint32_t n_tex;
     uint32_t is_signed;
-    // kInterleaved: the four pyramids share one geometry and their texel
-    // scratch is position-interleaved -- texel (x, y) of level l of all four
-    // pyramids in one 32-byte position (pyramid t at byte 8t), tex_off
+    // 1: the four pyramids share one geometry and their texel scratch is
+    // position-packed -- texel (x, y) of level l of all four pyramids in one
+    // 24-byte position of (r, g, b) halves (pyramid t at byte 6t), tex_off
     // counting positions and equal for every pyramid -- so a footprint row of
-    // all four pyramids is one 64-byte span (the batch scratch).
-    // kPacked: the same with the four pyramids' (r, g, b) halves packed into a
-    // 24-byte position (pyramid t at byte 6t), a footprint row a 48-byte span
-    // (a single material's scratch). 0: each pyramid's levels back to back
-    // (8-byte texels).
+    // all four pyramids is one 48-byte span. 0: each pyramid's levels back to
+    // back (8-byte texels (r | g << 16, b)).
     uint32_t interleaved;
 };
-constexpr uint32_t kInterleaved = 1, kPacked = 2;
 
 // MLP arithmetic variants
 enum MlpKind : uint32_t { MLP_VALU_F32 = 0, MLP_MFMA_F16 = 1, MLP_MFMA_BF16 = 2,
@@ -87,15 +83,14 @@ hipError_t launch_predecode(const MaterialDesc &m, const PredecodePlan &p, uint2
                             hipStream_t s);
 
 // One segment of an unpack: one level of one pyramid, or of all four
-// pyramids of a position-interleaved or packed scratch (kSegPacked with
-// kSegInterleaved: 24-byte positions).
-constexpr uint32_t kSegInterleaved = 1u, kSegSigned = 2u, kSegPacked = 4u;
+// pyramids of a position-packed scratch (kSegInterleaved).
+constexpr uint32_t kSegInterleaved = 1u, kSegSigned = 2u;
 struct UnpackSeg {
     const uint4 *blocks[kMaxTextures];  // the level's first block per pyramid slot (slot 0 unless interleaved)
     uint2 *texels;                      // the level's first texel (interleaved: first position)
     uint32_t lw, lh;                    // level size in texels
     uint32_t wg0;                       // the segment's first chunk of 256 lanes in its launch
-    uint32_t flags;                     // kSegInterleaved | kSegSigned | kSegPacked
+    uint32_t flags;                     // kSegInterleaved | kSegSigned
 };
 // every segment of a batch in one launch (segs in device memory, by first chunk)
 // chunk_seg[c] = the segment of chunk c (n_chunks entries)

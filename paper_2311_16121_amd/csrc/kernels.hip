@@ -155,13 +155,11 @@ __device__ __forceinline__ void unpack_chunk(const UnpackSeg &sg, uint32_t chunk
     };
     if (il) {
         // A wave holds 16 blocks (four lanes each, one per pyramid). Each
-        // block row is one 128-byte line of four 32-byte positions; a store
-        // instruction writes eight whole lines: lane L takes 16 bytes
-        // (position L % 8 / 2 of the row, pyramids 2(L%2) and 2(L%2)+1) of
+        // block row is four 24-byte positions, 96 contiguous bytes; a store
+        // instruction writes eight block rows: lane L takes the 12 bytes of
+        // pyramids 2(L%2) and 2(L%2)+1 at position L % 8 / 2 of the row of
         // block 8h + L / 8, read through LDS from that block's lanes.
         // Non-temporal like the per-pyramid layout's stores.
-        // packed: 24-byte positions, lane L's two pyramids 12 bytes of them
-        const bool packed = (sg.flags & kSegPacked) != 0;
         uint32_t *pdst = reinterpret_cast<uint32_t *>(sg.texels);
         const uint32_t lane = threadIdx.x & 63u, wave0 = threadIdx.x & ~63u;
         const uint32_t chunk8 = lane & 7u, pp = 2 * (lane & 1u), cpos = chunk8 >> 1;
@@ -172,7 +170,6 @@ __device__ __forceinline__ void unpack_chunk(const UnpackSeg &sg, uint32_t chunk
             const uint32_t bj = list ? list[p] : ((li - lane) >> 2) + blw;   // its index in the level
             const uint32_t lb = wave0 + 4 * blw + pp;                     // LDS lane of pyramid pp
             const uint32_t x0 = 4 * (bj & bxm), y0 = 4 * (bj >> bxs);
-            uint2 *dst = sg.texels + pp;
             for (uint32_t r = 0; r < 4; ++r) {
                 if (y0 + r >= lh) break;
                 // position index within the level (below 2^31: levels are at most 32768^2)
@@ -182,14 +179,9 @@ __device__ __forceinline__ void unpack_chunk(const UnpackSeg &sg, uint32_t chunk
                 if (lw == 1 && cpos >= 3) continue;
                 const uint32_t col = lw >= 4 ? cpos : lw == 2 ? (cpos & 1u) : 0u;
                 const uint2 p0 = texel(lb, 4 * r + col), p1 = texel(lb + 1, 4 * r + col);
-                const bool wrap = lw >= 4 && x0 == 0 && cpos < 2;           // also positions w, w + 1
-                if (packed) {
-                    store_packed_pair(pdst + 6 * (size_t)(prow + x0 + cpos) + 3 * (pp >> 1), p0, p1);
-                    if (wrap) store_packed_pair(pdst + 6 * (size_t)(prow + lw + cpos) + 3 * (pp >> 1), p0, p1);
-                } else {
-                    store_pair(dst + (size_t)kMaxTextures * (prow + x0 + cpos), p0, p1);
-                    if (wrap) store_pair(dst + (size_t)kMaxTextures * (prow + lw + cpos), p0, p1);
-                }
+                store_packed_pair(pdst + 6 * (size_t)(prow + x0 + cpos) + 3 * (pp >> 1), p0, p1);
+                if (lw >= 4 && x0 == 0 && cpos < 2)                        // wrap positions w, w + 1
+                    store_packed_pair(pdst + 6 * (size_t)(prow + lw + cpos) + 3 * (pp >> 1), p0, p1);
             }
         }
         return;
@@ -255,11 +247,10 @@ __device__ __forceinline__ UnpackSeg material_seg(const PredecodeArgs &a, uint32
     const TexDesc &T0 = a.m.tex[il ? 0u : a.p.seg_tex[seg]];
     sg.lw = max(T0.w >> l, 1u);
     sg.lh = max(T0.h >> l, 1u);
-    // 8-byte units per position: 4 interleaved, 3 packed, 1 per pyramid
-    const size_t unit = il == kPacked ? 3u : il ? (size_t)kMaxTextures : 1u;
-    sg.texels = a.texels + unit * T0.tex_off[l];
+    // 8-byte units per position: 3 packed, 1 per pyramid
+    sg.texels = a.texels + (il ? 3u : 1u) * (size_t)T0.tex_off[l];
     sg.wg0 = a.p.seg_wg[seg];
-    sg.flags = il ? (kSegInterleaved | (il == kPacked ? kSegPacked : 0u)) : 0u;
+    sg.flags = il ? kSegInterleaved : 0u;
     return sg;
 }
 
@@ -595,7 +586,7 @@ static FrameArgs frame_args(const MaterialDesc &m, const WsLayout &lay, const vo
         for (uint32_t l = 0; l < A.levels && shared; ++l)
             if (B.tex_off[l] != A.tex_off[l] + t * stride_texels) shared = false;
     }
-    *layout = m.interleaved == kPacked ? kLayoutPacked : shared ? kLayoutShared : kLayoutSplit;
+    *layout = m.interleaved ? kLayoutPacked : shared ? kLayoutShared : kLayoutSplit;
     a.stride = stride_texels * 8u;
     a.ws = static_cast<const uint8_t *>(ws);
     a.lay = lay;
