@@ -278,7 +278,7 @@ def bench_batch(args):
     c = spec.dims[-1]
     step_bytes = n * 12 + n * 4 * c + 16 * alg_blocks     # queries, outputs, every touched block once
     blocks = sum(4 * synth.chain_blocks(r, r, synth.full_levels(r, r)) for r in spec.res)
-    unpack_bytes = blocks * (16 + 16 * 8)
+    unpack_bytes = blocks * (16 + 16 * 6)          # every block in, its 16 texels' (r, g, b) halves out
     achieved = step_bytes / (decode_ms * 1e-3) / 1e9
     line = {
         "metric": "decoded queries/s, 64 materials per graph-captured step: unpack of the touched blocks, one "
@@ -634,8 +634,8 @@ def bench_frame(args):
     geo = [((r, r), L, b) for r, L, b in zip(m.res, m.levels, m.lod_bias)]
     U, T, NB = unique_blocks(geo, q), unique_texels(geo, q), all_blocks(geo)
     step_bytes = n * 12 + n * 4 * c + 16 * U           # the path: queries, outputs, touched blocks once
-    scratch_bytes = n * 12 + n * 4 * c + 8 * T         # the filter kernel's own reads: unpacked texels once
-    unpack_bytes = NB * (16 + 16 * 8)                  # every block in, its 16 texels out
+    scratch_bytes = n * 12 + n * 4 * c + 6 * T         # the filter kernel's own reads: unpacked texels once
+    unpack_bytes = NB * (16 + 16 * 6)                  # every block in, its 16 texels' (r, g, b) halves out
     mlp_flops = 2 * sum(x * y for x, y in zip(m.dims[:-1], m.dims[1:])) * n     # MLP multiply-adds x 2
 
     def roof(kernel, nbytes, kms, traffic=None):
