@@ -101,11 +101,18 @@ typedef uint32_t u32x3_t __attribute__((ext_vector_type(3)));
 typedef __attribute__((address_space(1))) u32x3_t global_u32x3;
 
 // Two pyramids' texels of one position of a packed scratch, (r, g, b) halves
-// each, as one 12-byte non-temporal store (dst 4-byte aligned).
+// each, as one 12-byte store (dst 4-byte aligned). NT: non-temporal. A single
+// material's unpack stores ordinarily: the decode that reads the scratch next
+// runs faster when the unpack's lines went through the caches (frame4k, 134
+// MB of scratch: 161 -> 138 us for the decode, 44 -> 50 us for the unpack).
+// A batch's unpacks, gigabytes of scratch, store non-temporally (batch64: the
+// decode 2.85 -> 2.79 ms, the whole unpack 4.06 -> 3.45 ms).
+template <bool NT>
 __device__ __forceinline__ void store_packed_pair(uint32_t *dst, uint2 t0, uint2 t1)
 {
     const u32x3_t v = {t0.x, (t0.y & 0xFFFFu) | (t1.x << 16), (t1.x >> 16) | (t1.y << 16)};
-    __builtin_nontemporal_store(v, (global_u32x3 *)dst);
+    if (NT) __builtin_nontemporal_store(v, (global_u32x3 *)dst);
+    else *(global_u32x3 *)dst = v;
 }
 
 // One chunk (256 lanes) of one unpack segment into the texel scratch. The
@@ -113,7 +120,7 @@ __device__ __forceinline__ void store_packed_pair(uint32_t *dst, uint2 t0, uint2
 // the workgroup's LDS, `table` the mode table. With `list` (LDS, interleaved
 // segments only) the chunk is instead the block positions list[0..n_list)
 // of the segment (at most 64), four lanes each; `chunk` is then unused.
-template <bool SIGNED>
+template <bool SIGNED, bool NT>
 __device__ __forceinline__ void unpack_chunk(const UnpackSeg &sg, uint32_t chunk, const uint32_t *table,
                                              uint2 (*palette)[256], uint2 *slots, const uint32_t *list = nullptr,
                                              uint32_t n_list = 0)
@@ -159,7 +166,7 @@ __device__ __forceinline__ void unpack_chunk(const UnpackSeg &sg, uint32_t chunk
         // instruction writes eight block rows: lane L takes the 12 bytes of
         // pyramids 2(L%2) and 2(L%2)+1 at position L % 8 / 2 of the row of
         // block 8h + L / 8, read through LDS from that block's lanes.
-        // Non-temporal like the per-pyramid layout's stores.
+        // The store policy: store_packed_pair.
         uint32_t *pdst = reinterpret_cast<uint32_t *>(sg.texels);
         const uint32_t lane = threadIdx.x & 63u, wave0 = threadIdx.x & ~63u;
         const uint32_t chunk8 = lane & 7u, pp = 2 * (lane & 1u), cpos = chunk8 >> 1;
@@ -179,9 +186,9 @@ __device__ __forceinline__ void unpack_chunk(const UnpackSeg &sg, uint32_t chunk
                 if (lw == 1 && cpos >= 3) continue;
                 const uint32_t col = lw >= 4 ? cpos : lw == 2 ? (cpos & 1u) : 0u;
                 const uint2 p0 = texel(lb, 4 * r + col), p1 = texel(lb + 1, 4 * r + col);
-                store_packed_pair(pdst + 6 * (size_t)(prow + x0 + cpos) + 3 * (pp >> 1), p0, p1);
+                store_packed_pair<NT>(pdst + 6 * (size_t)(prow + x0 + cpos) + 3 * (pp >> 1), p0, p1);
                 if (lw >= 4 && x0 == 0 && cpos < 2)                        // wrap positions w, w + 1
-                    store_packed_pair(pdst + 6 * (size_t)(prow + lw + cpos) + 3 * (pp >> 1), p0, p1);
+                    store_packed_pair<NT>(pdst + 6 * (size_t)(prow + lw + cpos) + 3 * (pp >> 1), p0, p1);
             }
         }
         return;
@@ -268,7 +275,7 @@ __global__ void __launch_bounds__(256) k_predecode(PredecodeArgs a)
     uint32_t seg = 0;
     while (seg + 1 < a.p.n_seg && a.p.seg_wg[seg + 1] <= wg) ++seg;
     const UnpackSeg sg = material_seg(a, seg);
-    unpack_chunk<SIGNED>(sg, wg - sg.wg0, table, palette, slots);
+    unpack_chunk<SIGNED, false>(sg, wg - sg.wg0, table, palette, slots);
 }
 
 // Every material of a batch in one launch: workgroup c unpacks chunk c of
@@ -287,8 +294,8 @@ __global__ void __launch_bounds__(256) k_predecode_batch(const UnpackSeg *segs, 
     load_table(table);
     for (uint32_t c = blockIdx.x; c < n_chunks; c += gridDim.x) {
         const UnpackSeg sg = segs[chunk_seg[c]];
-        if (sg.flags & kSegSigned) unpack_chunk<true>(sg, c - sg.wg0, table, palette, slots);
-        else unpack_chunk<false>(sg, c - sg.wg0, table, palette, slots);
+        if (sg.flags & kSegSigned) unpack_chunk<true, true>(sg, c - sg.wg0, table, palette, slots);
+        else unpack_chunk<false, true>(sg, c - sg.wg0, table, palette, slots);
         __syncthreads();                          // palette and slots are reused by the next chunk
     }
 }
@@ -316,8 +323,8 @@ __global__ void __launch_bounds__(256) k_predecode_touched(const UnpackSeg *segs
         const UnpackSeg sg = segs[sidx];
         const bool sgn = (sg.flags & kSegSigned) != 0;
         if (!(sg.flags & kSegInterleaved)) {
-            if (sgn) unpack_chunk<true>(sg, c0 - sg.wg0, table, palette, slots);
-            else unpack_chunk<false>(sg, c0 - sg.wg0, table, palette, slots);
+            if (sgn) unpack_chunk<true, true>(sg, c0 - sg.wg0, table, palette, slots);
+            else unpack_chunk<false, true>(sg, c0 - sg.wg0, table, palette, slots);
             __syncthreads();                      // palette and slots are reused by the next unit
             continue;
         }
@@ -340,8 +347,8 @@ __global__ void __launch_bounds__(256) k_predecode_touched(const UnpackSeg *segs
         __syncthreads();
         for (uint32_t p0 = 0; p0 < total; p0 += 64) {
             const uint32_t n = min(64u, total - p0);
-            if (sgn) unpack_chunk<true>(sg, 0, table, palette, slots, list + p0, n);
-            else unpack_chunk<false>(sg, 0, table, palette, slots, list + p0, n);
+            if (sgn) unpack_chunk<true, true>(sg, 0, table, palette, slots, list + p0, n);
+            else unpack_chunk<false, true>(sg, 0, table, palette, slots, list + p0, n);
             __syncthreads();
         }
     }
