@@ -668,33 +668,53 @@ hipError_t launch_filter_mlp(const MaterialDesc &m, const MlpShape &sh, MlpKind 
 
 size_t batch_table_bytes(uint32_t n_mats) { return sizeof(BatchMat) * n_mats; }
 
-// First work item of every material (runs of 64 queries), one lane.
-__global__ void k_batch_items(BatchArgs a)
+// First work item of every material (runs of 64 queries): one wave, an
+// exclusive prefix sum over 64 materials at a time.
+__global__ void __launch_bounds__(64) k_batch_items(BatchArgs a)
 {
-    if (threadIdx.x != 0) return;
-    uint32_t acc = 0;
-    for (uint32_t k = 0; k < a.n_mats; ++k) {
-        a.items[k] = acc;
-        uint32_t q0, cnt;
-        batch_range(a, k, q0, cnt);
-        acc += (cnt + 63u) / 64u;
+    const uint32_t lane = threadIdx.x;
+    uint32_t carry = 0;
+    for (uint32_t k0 = 0; k0 < a.n_mats; k0 += 64) {
+        const uint32_t k = k0 + lane;
+        uint32_t cnt = 0;
+        if (k < a.n_mats) {
+            uint32_t q0, c;
+            batch_range(a, k, q0, c);
+            cnt = (c + 63u) / 64u;
+        }
+        uint32_t v = cnt;                         // inclusive scan across the wave
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t t = __shfl_up(v, d);
+            if (lane >= (uint32_t)d) v += t;
+        }
+        if (k < a.n_mats) a.items[k] = carry + v - cnt;
+        carry += __shfl(v, 63);
     }
-    a.items[a.n_mats] = acc;
+    if (lane == 0) a.items[a.n_mats] = carry;
 }
 
-// Marks, for the position-interleaved materials of a batch, the block
-// positions the queries' footprints read: the same work items, levels and taps
-// as k_batch (items of 64 queries; a lane past a material's queries reads the
+// Marks, for the position-packed materials of a batch, the block positions
+// the queries' footprints read: the same work items, levels and taps as
+// k_batch (items of 64 queries; a lane past a material's queries reads the
 // query (0, 0, 0), as k_batch's does). marks[64 c + p] = 1 for position p of
 // unpack chunk c. Byte stores: concurrent marks of one position store the
 // same value. Each wave walks a contiguous range of items with its current
 // material's level table in LDS, loading the next item's queries while it
-// marks the current one's.
+// marks the current one's. The coarse levels (at most kPrivPositions block
+// positions each, most of the footprints) are marked in a wave-private byte
+// map in LDS and written out once per material the wave leaves.
+constexpr uint32_t kPrivPositions = 4096, kPrivBytes = 8192;
+
 __global__ void __launch_bounds__(256) k_batch_mark(BatchArgs a, uint8_t *marks)
 {
     __shared__ uint4 lut[4][kMaxLevels];
     __shared__ uint32_t segc[4][kMaxLevels];
+    __shared__ uint32_t poff[4][kMaxLevels], pcnt[4][kMaxLevels];   // private map: offset (~0: none), positions
+    __shared__ uint32_t priv[4][kPrivBytes / 4];
     const uint32_t lane = threadIdx.x & 63u, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    uint8_t *pm = reinterpret_cast<uint8_t *>(priv[wv]);
+    for (uint32_t i = lane; i < kPrivBytes / 4; i += 64) priv[wv][i] = 0u;
     const uint32_t total = a.items[a.n_mats];
     const uint32_t waves = gridDim.x * 4, w = blockIdx.x * 4 + wv;
     const uint32_t first = (uint32_t)((uint64_t)total * w / waves), end = (uint32_t)((uint64_t)total * (w + 1) / waves);
@@ -724,6 +744,33 @@ __global__ void __launch_bounds__(256) k_batch_mark(BatchArgs a, uint8_t *marks)
         base = uniform(a.items[k]);
         next = uniform(a.items[k + 1]);
         wave_lds_sync();
+        if (lane == 0) {                            // the private levels, coarsest first
+            const uint32_t levels = __builtin_bit_cast(uint32_t, lb0);
+            uint32_t used = 0;
+            for (uint32_t l = kMaxLevels; l-- > 0;) {
+                const uint32_t masks = lut[wv][l].z;
+                const uint32_t n = (((masks & 0xFFFFu) + 4u) >> 2) * (((masks >> 16) + 4u) >> 2);
+                const bool take = interleaved && l < levels && n <= kPrivPositions && used + n <= kPrivBytes;
+                poff[wv][l] = take ? used : 0xFFFFFFFFu;
+                pcnt[wv][l] = n;
+                used += take ? n : 0u;
+            }
+        }
+        wave_lds_sync();
+    };
+    auto flush = [&]() {                            // the private map to memory, cleared
+        for (uint32_t l = 0; l < (uint32_t)kMaxLevels; ++l) {
+            const uint32_t off = poff[wv][l];
+            if (off == 0xFFFFFFFFu) continue;
+            uint8_t *mk = marks + 64ull * segc[wv][l];
+            for (uint32_t p = lane; p < pcnt[wv][l]; p += 64) {
+                if (pm[off + p]) {
+                    mk[p] = 1;
+                    pm[off + p] = 0;
+                }
+            }
+        }
+        wave_lds_sync();
     };
     enter(lo);
     Query q = load_query(rq, (first - base) * 64 + lane);
@@ -743,17 +790,22 @@ __global__ void __launch_bounds__(256) k_batch_mark(BatchArgs a, uint8_t *marks)
                 const uint32_t xa = tc.x0 >> 2, xb = ((tc.x0 + 1u) & tc.wm) >> 2;   // column w is column 0
                 const uint32_t ya = tc.y0 >> 2, yb = tc.y1 >> 2;
                 // most footprints lie in one block: store each distinct position once
-                uint8_t *mk = marks + 64ull * segc[wv][l];
-                mk[ya * bxn + xa] = 1;
-                if (xb != xa) mk[ya * bxn + xb] = 1;
-                if (yb != ya) {
-                    mk[yb * bxn + xa] = 1;
-                    if (xb != xa) mk[yb * bxn + xb] = 1;
-                }
+                const uint32_t off = poff[wv][l];
+                auto mark = [&](uint8_t *mk) {
+                    mk[ya * bxn + xa] = 1;
+                    if (xb != xa) mk[ya * bxn + xb] = 1;
+                    if (yb != ya) {
+                        mk[yb * bxn + xa] = 1;
+                        if (xb != xa) mk[yb * bxn + xb] = 1;
+                    }
+                };
+                if (off != 0xFFFFFFFFu) mark(pm + off);           // LDS
+                else mark(marks + 64ull * segc[wv][l]);          // memory
             }
         }
         if (nx < end && !same) {                    // the next item starts another material
-            wave_lds_sync();                        // this item's LDS reads are done
+            wave_lds_sync();                        // this item's LDS reads and marks are done
+            flush();
             uint32_t k = lo + 1;
             while (k + 1 < a.n_mats && a.items[k + 1] <= nx) ++k;   // past empty materials
             lo = uniform(k);
@@ -762,6 +814,8 @@ __global__ void __launch_bounds__(256) k_batch_mark(BatchArgs a, uint8_t *marks)
         }
         q = qn;
     }
+    wave_lds_sync();
+    flush();
 }
 
 __global__ void __launch_bounds__(256) k_fill_u32x4(u32x4_t *p, size_t n)
