@@ -400,13 +400,6 @@ bcf_status describe_train(const bcf_train_material *m, bcf::TrainDesc *d, size_t
             td.tex_off[l] = (uint32_t)texels;
             texels += (size_t)level_dim(x.width, l) * level_dim(x.height, l);
         }
-        // the smallest levels that together hold at most kTrainSmallTexels texels
-        d->small_hi[t] = (uint32_t)texels;
-        d->small_lo[t] = (uint32_t)texels;
-        for (uint32_t l = x.levels; l-- > 0;) {
-            if (texels - td.tex_off[l] > bcf::kTrainSmallTexels) break;
-            d->small_lo[t] = td.tex_off[l];
-        }
     }
     d->blk_base[m->n_textures] = (uint32_t)blocks;
     if (texels > ((size_t)1 << 27)) return fail(BCF_ERR_UNSUPPORTED, "%zu texels, at most 2^27", texels);
@@ -437,18 +430,28 @@ bcf_status describe_train(const bcf_train_material *m, bcf::TrainDesc *d, size_t
     }
     d->dims[m->n_layers] = out;
     d->n_params = off;
-    *ws_bytes = 2 * align_up(texels * 16, 256);
+    *ws_bytes = 2 * align_up(texels * 16, 256) + align_up((size_t)bcf::kTrainBinBatch * 4, 256) +
+                2 * align_up((size_t)bcf::kTrainBins * 4, 256) + (size_t)bcf::kTrainBinBatch * 48;
     return BCF_OK;
 }
 
 // The workspace holds bcf_train_workspace_size bytes (the caller's promise):
-// the texel values, then their gradients.
+// the texel values, their gradients, then the backward's sample sort.
 bcf_status bind_train_ws(bcf::TrainDesc *d, void *ws)
 {
     if (!ws || !aligned(ws, 256)) return fail(BCF_ERR_INVALID_ARG, "workspace NULL or not 256-byte aligned");
     uint8_t *p = static_cast<uint8_t *>(ws);
+    const size_t img = align_up((size_t)d->n_texels * 16, 256);
     d->texels = reinterpret_cast<float4 *>(p);
-    d->g_texels = reinterpret_cast<float4 *>(p + align_up((size_t)d->n_texels * 16, 256));
+    d->g_texels = reinterpret_cast<float4 *>(p + img);
+    p += 2 * img;
+    d->bin_perm = reinterpret_cast<uint32_t *>(p);
+    p += align_up((size_t)bcf::kTrainBinBatch * 4, 256);
+    d->bin_count = reinterpret_cast<uint32_t *>(p);
+    p += align_up((size_t)bcf::kTrainBins * 4, 256);
+    d->bin_next = reinterpret_cast<uint32_t *>(p);
+    p += align_up((size_t)bcf::kTrainBins * 4, 256);
+    d->bin_dz = reinterpret_cast<float *>(p);
     return BCF_OK;
 }
 

@@ -4,8 +4,13 @@
 //
 //   k_train_texels    block parameters -> texel images (r, g, b, 0) per level
 //   k_train_forward   queries -> G(u, v, s), one lane per query
-//   k_train_backward  queries, dL/dG -> dL/d texel (float atomics) and
-//                     dL/d MLP parameters (per-wave sums through LDS)
+//   k_train_bin_*     the backward's samples sorted by position (counting
+//                     sort over a grid of cells on the wrapped (u, v))
+//   k_train_backward  queries, dL/dG -> dL/d features per sample and dL/d MLP
+//                     parameters (per-wave sums through LDS)
+//   k_train_scatter   dL/d features -> dL/d texel, one workgroup per cell:
+//                     sums in LDS windows over the cell's footprint, then
+//                     one float atomic per touched texel channel
 //   k_train_blocks    dL/d texel -> dL/d endpoints, dL/d indices (one lane
 //                     per texel, sums over a block's 16 lanes by shuffles)
 //
@@ -17,6 +22,8 @@
 // rounding taken as the identity and eq. (8)'s slope at the decoded bits.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "bc6h_device.hpp"
 #include "train.hpp"
 
@@ -26,8 +33,7 @@ namespace {
 constexpr float kA = 31.0f / 64.0f;      // a of eq. (6) for the unsigned format
 constexpr int kTrainThreads = 256;
 // the backward runs three waves per workgroup: its LDS (per-wave reduction
-// buffers, the privatised small levels, the MLP and the level table, ≈ 77 KB)
-// then fits two workgroups per CU
+// buffers, the MLP and the level table, ≈ 60 KB) then fits two workgroups per CU
 constexpr int kBwdThreads = 192;
 constexpr int kBwdWaves = kBwdThreads / 64;
 
@@ -225,7 +231,7 @@ __device__ __forceinline__ void load_level_lut(const TrainDesc &d, TrainLevelLut
 // The 32 taps of a query (4 pyramids x 2 levels x 4 texels): texel index and
 // weight (bilinear times trilinear); pyramids past n_tex get weight 0.
 __device__ __forceinline__ void taps(const TrainDesc &d, const TrainLevelLut &lut, float u, float v, float s,
-                                     uint32_t idx[32], float wt[32])
+                                     uint32_t idx[32], float wt[32], uint32_t lvl[8] = nullptr)
 {
     const float uf = u - floorf(u), vf = v - floorf(v);          // wrap addressing
 #pragma unroll
@@ -241,6 +247,7 @@ __device__ __forceinline__ void taps(const TrainDesc &d, const TrainLevelLut &lu
         for (int k = 0; k < 2; ++k) {
             const uint32_t l = k ? l1 : l0;
             const float lw = on * (k ? lam : 1.0f - lam);
+            if (lvl) lvl[2 * ti + k] = l;
             const uint4 e = lut[slot][l];
             const uint32_t wl = e.x, hl = e.y;
             const float x = fmaf(uf, (float)wl, -0.5f), y = fmaf(vf, (float)hl, -0.5f);
@@ -440,24 +447,104 @@ __device__ __forceinline__ void flush(const float acc[K], float *g, uint32_t n_i
     }
 }
 
+// ---------------------------------------------------------------------------
+// the backward's sample order
+//
+// Texel-gradient float atomics on random lines of levels larger than the
+// caches each fetch and write back a whole line. Taking the samples cell by
+// cell (and each XCD a contiguous run of cells) lets the samples that share
+// gradient lines update them while the lines sit in one L2.
+
+constexpr int kBinThreads = 1024;
+
+// A query's cell: its wrapped (u, v) on the kTrainBinSide grid (NaN and
+// infinities land in cell 0), numbered along a Z-order curve.
+__device__ __forceinline__ uint32_t bin_of(float u, float v)
+{
+    const float uf = u - floorf(u), vf = v - floorf(v);
+    const float side = (float)kTrainBinSide;
+    const uint32_t cx = (uint32_t)fminf(fmaxf(uf * side, 0.0f), side - 1.0f);
+    const uint32_t cy = (uint32_t)fminf(fmaxf(vf * side, 0.0f), side - 1.0f);
+    uint32_t z = 0;
+#pragma unroll
+    for (uint32_t b = 0; b < 6; ++b) z |= ((cx >> b) & 1u) << (2 * b) | ((cy >> b) & 1u) << (2 * b + 1);
+    return z;
+}
+
+// count[cell] += samples of the cell; one sample per thread, a histogram in LDS per workgroup
+__global__ void __launch_bounds__(kBinThreads) k_train_bin_count(const float *queries, uint32_t n, uint32_t *count)
+{
+    __shared__ uint32_t hist[kTrainBins];
+    for (uint32_t b = threadIdx.x; b < kTrainBins; b += kBinThreads) hist[b] = 0u;
+    __syncthreads();
+    const uint32_t i = blockIdx.x * kBinThreads + threadIdx.x;
+    if (i < n) atomicAdd(&hist[bin_of(queries[3u * i], queries[3u * i + 1u])], 1u);
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b < kTrainBins; b += kBinThreads)
+        if (hist[b]) atomicAdd(&count[b], hist[b]);
+}
+
+// next[cell] = samples of the cells before it (one workgroup, 4 cells a thread)
+__global__ void __launch_bounds__(kBinThreads) k_train_bin_scan(const uint32_t *count, uint32_t *next)
+{
+    static_assert(kTrainBins == 4 * kBinThreads, "four cells a thread");
+    __shared__ uint32_t wave_sum[kBinThreads / 64];
+    const uint32_t t = threadIdx.x, lane = t & 63u, wv = t >> 6;
+    uint32_t c[4], own = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        c[k] = count[4 * t + k];
+        own += c[k];
+    }
+    uint32_t incl = own;                           // inclusive scan within the wave
+#pragma unroll
+    for (uint32_t d = 1; d < 64; d <<= 1) {
+        const uint32_t o = __shfl_up(incl, d);
+        if (lane >= d) incl += o;
+    }
+    if (lane == 63) wave_sum[wv] = incl;
+    __syncthreads();
+    uint32_t base = 0;
+    for (uint32_t w = 0; w < wv; ++w) base += wave_sum[w];
+    uint32_t run = base + incl - own;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        next[4 * t + k] = run;
+        run += c[k];
+    }
+}
+
+// perm[next[cell]++] = sample: each workgroup ranks its samples per cell in
+// LDS, then reserves one run per cell it holds
+__global__ void __launch_bounds__(kBinThreads) k_train_bin_scatter(const float *queries, uint32_t n, uint32_t *next,
+                                                                   uint32_t *perm)
+{
+    __shared__ uint32_t hist[kTrainBins];
+    for (uint32_t b = threadIdx.x; b < kTrainBins; b += kBinThreads) hist[b] = 0u;
+    __syncthreads();
+    const uint32_t i = blockIdx.x * kBinThreads + threadIdx.x;
+    const uint32_t bin = i < n ? bin_of(queries[3u * i], queries[3u * i + 1u]) : 0u;
+    const uint32_t rank = i < n ? atomicAdd(&hist[bin], 1u) : 0u;
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b < kTrainBins; b += kBinThreads)
+        if (hist[b]) hist[b] = atomicAdd(&next[b], hist[b]);
+    __syncthreads();
+    if (i < n) perm[hist[bin] + rank] = i;
+}
+
 template <int H, int NH>
 __global__ void __launch_bounds__(kBwdThreads, 2) k_train_backward(TrainDesc d, const float *queries, uint32_t n,
-                                                                const float *grad_out)
+                                                                const float *grad_out, const uint32_t *perm)
 {
     constexpr int K0 = entries_per_lane(12, H);
     constexpr int KH = entries_per_lane(H, H);
     constexpr int KL = entries_per_lane(H, kMaxOut);
     __shared__ float lds_a[kBwdWaves][64][kTrainMaxHidden + 1];
     __shared__ float lds_d[kBwdWaves][64][kTrainMaxHidden];
-    // Gradients of each pyramid's smallest levels (texels small_lo..small_hi):
-    // every query that reaches them hits the same few texels, so they are
-    // summed in LDS per workgroup and added to memory once at the end.
-    __shared__ float small[kMaxTextures * kTrainSmallTexels * 3];
     __shared__ MlpLds<H, NH> mlp;
     __shared__ TrainLevelLut lut;
-    for (uint32_t i = threadIdx.x; i < kMaxTextures * kTrainSmallTexels * 3; i += kBwdThreads) small[i] = 0.0f;
     load_level_lut(d, lut);
-    load_mlp<H, NH>(d, mlp);                  // synchronises, also for `small` and `lut`
+    load_mlp<H, NH>(d, mlp);                  // synchronises, also for `lut`
 
     const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
     const uint32_t n0 = d.dims[0], c = d.dims[NH + 1];
@@ -473,10 +560,16 @@ __global__ void __launch_bounds__(kBwdThreads, 2) k_train_backward(TrainDesc d, 
 
     float (*a)[kTrainMaxHidden + 1] = lds_a[wv];
     float (*dl)[kTrainMaxHidden] = lds_d[wv];
-    const uint32_t n_chunks = (n + 63u) / 64u;
-    for (uint32_t ch = blockIdx.x * kBwdWaves + wv; ch < n_chunks; ch += gridDim.x * kBwdWaves) {
-        const uint32_t q = ch * 64u + lane;
-        const bool live = q < n;
+    // Samples in the sorted order, 64 per wave; workgroups are dealt to the
+    // 8 XCDs in turn (the grid is a multiple of 8), and XCD x takes the x-th
+    // eighth of the order.
+    const uint32_t n_chunks = (n + 63u) / 64u, xcd = blockIdx.x & 7u, xcd_wgs = gridDim.x >> 3;
+    const uint32_t c_end = (uint32_t)((uint64_t)n_chunks * (xcd + 1u) / 8u);
+    for (uint32_t ch = (uint32_t)((uint64_t)n_chunks * xcd / 8u) + (blockIdx.x >> 3) * kBwdWaves + wv; ch < c_end;
+         ch += xcd_wgs * kBwdWaves) {
+        const uint32_t slot = ch * 64u + lane;
+        const bool live = slot < n;
+        const uint32_t q = live ? perm[slot] : 0u;
         const float u = live ? queries[3u * q] : 0.0f;
         const float v = live ? queries[3u * q + 1u] : 0.0f;
         const float s = live ? queries[3u * q + 2u] : 0.0f;
@@ -547,7 +640,7 @@ __global__ void __launch_bounds__(kBwdThreads, 2) k_train_backward(TrainDesc d, 
             else accumulate<KH>(accH[l > 0 ? l - 1 : 0], a, dl, H, H, lane);
             wave_sync_lds();
         }
-        // dL/dz = W_0^T delta, then onto the 32 taps
+        // dL/dz = W_0^T delta
         float dz[12];
 #pragma unroll
         for (int i = 0; i < 12; ++i) dz[i] = 0.0f;
@@ -559,40 +652,133 @@ __global__ void __launch_bounds__(kBwdThreads, 2) k_train_backward(TrainDesc d, 
             for (int i = 0; i < 12; ++i) dz[i] = fmaf(w[i], delta[j], dz[i]);
             pin(dz);
         }
+        // dL/dz in the sorted order, for the scatter
         if (live) {
-            uint32_t idx[32];
-            float wt[32];
-            taps(d, lut, u, v, s, idx, wt);
-#pragma unroll
-            for (int k = 0; k < 32; ++k) {
-                const int t = k / 8;
-                if (t < (int)d.n_tex) {
-                    const uint32_t rel = idx[k] - d.small_lo[t];
-                    if (rel < d.small_hi[t] - d.small_lo[t]) {
-                        float *sp = small + (t * kTrainSmallTexels + rel) * 3;
-                        atomicAdd(sp + 0, wt[k] * dz[3 * t + 0]);
-                        atomicAdd(sp + 1, wt[k] * dz[3 * t + 1]);
-                        atomicAdd(sp + 2, wt[k] * dz[3 * t + 2]);
-                    } else {
-                        float *gp = reinterpret_cast<float *>(d.g_texels + idx[k]);
-                        unsafeAtomicAdd(gp + 0, wt[k] * dz[3 * t + 0]);
-                        unsafeAtomicAdd(gp + 1, wt[k] * dz[3 * t + 1]);
-                        unsafeAtomicAdd(gp + 2, wt[k] * dz[3 * t + 2]);
-                    }
-                }
-            }
+            float4 *dst = reinterpret_cast<float4 *>(d.bin_dz + 12u * (size_t)slot);
+            dst[0] = make_float4(dz[0], dz[1], dz[2], dz[3]);
+            dst[1] = make_float4(dz[4], dz[5], dz[6], dz[7]);
+            dst[2] = make_float4(dz[8], dz[9], dz[10], dz[11]);
         }
-    }
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < kMaxTextures * kTrainSmallTexels * 3; i += kBwdThreads) {
-        const uint32_t t = i / (kTrainSmallTexels * 3), j = (i / 3) % kTrainSmallTexels, c = i % 3;
-        if (t < d.n_tex && j < d.small_hi[t] - d.small_lo[t] && small[i] != 0.0f)
-            unsafeAtomicAdd(reinterpret_cast<float *>(d.g_texels + d.small_lo[t] + j) + c, small[i]);
     }
     flush<K0>(acc0, d.g_params + d.w_off[0], n0, H, lane);
 #pragma unroll
     for (int l = 1; l < NH; ++l) flush<KH>(accH[l - 1], d.g_params + d.w_off[l], H, H, lane);
     flush<KL>(accL, d.g_params + d.w_off[NH], H, c, lane);
+}
+
+// ---------------------------------------------------------------------------
+// dL/dz -> dL/d texel
+
+constexpr int kScatterThreads = 256;
+constexpr uint32_t kWindowFloats = 8192;      // 32 KB of LDS windows per workgroup
+
+// A window of one (pyramid, level): the texels x0 .. x0 + w - 1 (wrapped) of
+// rows y0 .. y0 + h - 1, three floats each from `off` in the pool; off = ~0u:
+// the level's gradients go straight to memory.
+struct TexWindow {
+    uint32_t x0, y0, w, h, off;
+};
+
+// One workgroup per cell of the sample sort: the cell's samples (sorted
+// indices begin .. end) add wt * dL/dz to the texels of their taps. Every tap
+// of a cell's samples at one (pyramid, level) lies in a small box around the
+// cell's footprint, so the sums go to LDS windows over those boxes (the
+// coarsest levels first, while the pool lasts) and then to memory once per
+// touched texel channel; a tap outside its window (or of a level without one)
+// goes to memory directly.
+__global__ void __launch_bounds__(kScatterThreads) k_train_scatter(TrainDesc d, const float *queries)
+{
+    __shared__ float pool[kWindowFloats];
+    __shared__ TexWindow win[kMaxTextures][kMaxLevels];
+    __shared__ TrainLevelLut lut;
+    __shared__ uint32_t pool_used;
+    const uint32_t cell = blockIdx.x;
+    const uint32_t begin = cell ? d.bin_next[cell - 1] : 0u, end = d.bin_next[cell];
+    if (begin == end) return;                          // uniform over the workgroup
+    load_level_lut(d, lut);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // the cell's corner from its Z-order number
+        uint32_t cx = 0, cy = 0;
+#pragma unroll
+        for (uint32_t b = 0; b < 6; ++b) {
+            cx |= ((cell >> (2 * b)) & 1u) << b;
+            cy |= ((cell >> (2 * b + 1)) & 1u) << b;
+        }
+        uint32_t used = 0;
+        for (int l = kMaxLevels - 1; l >= 0; --l)
+            for (uint32_t t = 0; t < (uint32_t)kMaxTextures; ++t) {
+                TexWindow &W = win[t][l];
+                W.off = ~0u;
+                if (t >= d.n_tex || (uint32_t)l >= d.tex[t].levels) continue;
+                // a cell spans wl / side texels; its samples' taps span at
+                // most ceil of that + 2 columns from floor(cx wl / side - 0.5)
+                const uint32_t wl = lut[t][l].x, hl = lut[t][l].y;
+                const uint32_t ww = min(wl, (wl + kTrainBinSide - 1) / kTrainBinSide + 2u);
+                const uint32_t wh = min(hl, (hl + kTrainBinSide - 1) / kTrainBinSide + 2u);
+                const float fx = floorf((float)cx * ((float)wl / (float)kTrainBinSide) - 0.5f);
+                const float fy = floorf((float)cy * ((float)hl / (float)kTrainBinSide) - 0.5f);
+                W.x0 = ww == wl ? 0u : (uint32_t)(int)fx & (wl - 1u);
+                W.y0 = wh == hl ? 0u : (uint32_t)(int)fy & (hl - 1u);
+                W.w = ww;
+                W.h = wh;
+                if (used + 3u * ww * wh <= kWindowFloats) {
+                    W.off = used;
+                    used += 3u * ww * wh;
+                }
+            }
+        pool_used = used;
+    }
+    __syncthreads();
+    const uint32_t used = pool_used;
+    for (uint32_t e = threadIdx.x; e < used; e += kScatterThreads) pool[e] = 0.0f;
+    __syncthreads();
+    for (uint32_t j = begin + threadIdx.x; j < end; j += kScatterThreads) {
+        const uint32_t q = d.bin_perm[j];
+        const float4 *src = reinterpret_cast<const float4 *>(d.bin_dz + 12u * (size_t)j);
+        const float4 z0 = src[0], z1 = src[1], z2 = src[2];
+        const float dz[12] = {z0.x, z0.y, z0.z, z0.w, z1.x, z1.y, z1.z, z1.w, z2.x, z2.y, z2.z, z2.w};
+        uint32_t idx[32], lvl[8];
+        float wt[32];
+        taps(d, lut, queries[3u * q], queries[3u * q + 1u], queries[3u * q + 2u], idx, wt, lvl);
+#pragma unroll
+        for (int k = 0; k < 32; ++k) {
+            const int t = k / 8;
+            // a zero weight (an unused second level, a pyramid past n_tex) adds nothing
+            if (t >= (int)d.n_tex || wt[k] == 0.0f) continue;
+            const uint32_t l = lvl[k / 4];
+            const uint4 e = lut[t][l];
+            const uint32_t rel = idx[k] - e.z;             // y * wl + x, wl a power of two
+            const uint32_t x = rel & (e.x - 1u), y = rel >> __builtin_ctz(e.x);
+            const TexWindow W = win[t][l];
+            const uint32_t dx = (x - W.x0) & (e.x - 1u), dy = (y - W.y0) & (e.y - 1u);
+            if (W.off != ~0u && dx < W.w && dy < W.h) {
+                float *p = pool + W.off + 3u * (dy * W.w + dx);
+                atomicAdd(p + 0, wt[k] * dz[3 * t + 0]);
+                atomicAdd(p + 1, wt[k] * dz[3 * t + 1]);
+                atomicAdd(p + 2, wt[k] * dz[3 * t + 2]);
+            } else {
+                float *gp = reinterpret_cast<float *>(d.g_texels + idx[k]);
+                unsafeAtomicAdd(gp + 0, wt[k] * dz[3 * t + 0]);
+                unsafeAtomicAdd(gp + 1, wt[k] * dz[3 * t + 1]);
+                unsafeAtomicAdd(gp + 2, wt[k] * dz[3 * t + 2]);
+            }
+        }
+    }
+    __syncthreads();
+    for (uint32_t t = 0; t < d.n_tex; ++t)
+        for (uint32_t l = 0; l < d.tex[t].levels; ++l) {
+            const TexWindow W = win[t][l];
+            if (W.off == ~0u) continue;
+            const uint4 e = lut[t][l];
+            for (uint32_t i = threadIdx.x; i < 3u * W.w * W.h; i += kScatterThreads) {
+                const float v = pool[W.off + i];
+                if (v == 0.0f) continue;
+                const uint32_t p = i / 3u, c = i - 3u * p, dy = p / W.w, dx = p - dy * W.w;
+                const uint32_t x = (W.x0 + dx) & (e.x - 1u), y = (W.y0 + dy) & (e.y - 1u);
+                unsafeAtomicAdd(reinterpret_cast<float *>(d.g_texels + e.z + y * e.x + x) + c, v);
+            }
+        }
 }
 
 unsigned grid_for(size_t work, unsigned per_block, unsigned cap)
@@ -619,9 +805,10 @@ hipError_t forward_hn(const TrainDesc &d, const float *queries, uint32_t n, floa
 template <int H, int NH>
 hipError_t backward_hn(const TrainDesc &d, const float *queries, uint32_t n, const float *grad_out, hipStream_t s)
 {
-    // a few workgroups per CU: each flushes its parameter and small-level sums once
-    const unsigned grid = grid_for((n + 63u) / 64u, kBwdWaves, 768);
-    k_train_backward<H, NH><<<grid, kBwdThreads, 0, s>>>(d, queries, n, grad_out);
+    // a few workgroups per CU (each flushes its parameter and small-level
+    // sums once), a multiple of the 8 XCDs
+    const unsigned grid = (grid_for((n + 63u) / 64u, kBwdWaves, 768) + 7u) & ~7u;
+    k_train_backward<H, NH><<<grid, kBwdThreads, 0, s>>>(d, queries, n, grad_out, d.bin_perm);
     return hipGetLastError();
 }
 
@@ -668,7 +855,20 @@ hipError_t launch_train_backward(const TrainDesc &d, const float *queries, size_
         reinterpret_cast<float *>(d.g_texels), d.n_texels * 4u);
     k_train_zero<<<grid_for(d.n_params, 256, 64), 256, 0, s>>>(d.g_params, d.n_params);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (n > 0 && (e = dispatch_backward(d, queries, (uint32_t)n, grad_out, s)) != hipSuccess) return e;
+    const uint32_t c = d.dims[d.n_layers];
+    for (size_t off = 0; off < n; off += kTrainBinBatch) {
+        const uint32_t m = (uint32_t)std::min(n - off, (size_t)kTrainBinBatch);
+        const float *q = queries + 3 * off;
+        const unsigned bins = (m + kBinThreads - 1) / kBinThreads;
+        // (the counts are cleared as floats: 0.0f is all zero bits)
+        k_train_zero<<<8, 256, 0, s>>>(reinterpret_cast<float *>(d.bin_count), kTrainBins);
+        k_train_bin_count<<<bins, kBinThreads, 0, s>>>(q, m, d.bin_count);
+        k_train_bin_scan<<<1, kBinThreads, 0, s>>>(d.bin_count, d.bin_next);
+        k_train_bin_scatter<<<bins, kBinThreads, 0, s>>>(q, m, d.bin_next, d.bin_perm);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = dispatch_backward(d, q, m, grad_out + (size_t)c * off, s)) != hipSuccess) return e;
+        k_train_scatter<<<kTrainBins, kScatterThreads, 0, s>>>(d, q);
+    }
     const unsigned grid = grid_for((size_t)d.blk_base[d.n_tex] * 16u, kTrainThreads, 16384);
     if (d.ste) k_train_blocks<true><<<grid, kTrainThreads, 0, s>>>(d);
     else k_train_blocks<false><<<grid, kTrainThreads, 0, s>>>(d);

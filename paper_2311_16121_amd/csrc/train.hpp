@@ -12,8 +12,12 @@
 namespace bcf {
 
 constexpr int kTrainMaxHidden = 32;
-// texels of each pyramid's smallest levels whose gradients the backward sums in LDS
-constexpr uint32_t kTrainSmallTexels = 352;
+// The backward takes its samples in spatial order: per call of at most
+// kTrainBinBatch samples, a counting sort by cell of a kTrainBinSide^2 grid
+// over the wrapped (u, v), the cells numbered along a Z-order curve.
+constexpr uint32_t kTrainBinBatch = 1u << 20;
+constexpr uint32_t kTrainBinSide = 64;
+constexpr uint32_t kTrainBins = kTrainBinSide * kTrainBinSide;
 
 // One pyramid of continuous two-subset blocks (6-bit endpoints, 3-bit
 // indices, fixed partitions), all levels back to back.
@@ -44,9 +48,11 @@ struct TrainDesc {
     uint32_t dims[5];
     uint32_t n_layers;
     uint32_t w_off[4], b_off[4];   // float offsets of each layer's W and b in params
-    // per pyramid: its smallest levels, texels small_lo .. small_hi - 1 of the
-    // images (at most kTrainSmallTexels), summed per workgroup in LDS
-    uint32_t small_lo[kMaxTextures], small_hi[kMaxTextures];
+    // the backward's sample sort (workspace): sorted sample indices, per-cell
+    // counts, per-cell next free slot (after the sort: the end of the cell's
+    // run), and dL/dz (12 floats) per sorted sample
+    uint32_t *bin_perm, *bin_count, *bin_next;
+    float *bin_dz;
 };
 
 hipError_t launch_train_forward(const TrainDesc &d, const float *queries, size_t n, float *out,
