@@ -219,3 +219,58 @@ def test_autograd_function_and_a_few_training_steps(bcf):
         losses.append(float(loss))
     log(f"training losses: {losses[0]:.4e} -> {losses[-1]:.4e}")
     assert losses[-1] < 0.5 * losses[0]
+
+
+def special_train_queries(g, n, s_max):
+    """Queries on and around the 64 x 64 cells the backward sorts its samples
+    into, wrapped from outside [0, 1), and at the ends of the LOD range."""
+    k = g.integers(0, 65, (n, 2)).astype(np.float64) / 64.0
+    eps = g.choice([0.0, 1e-7, -1e-7, 3e-5, -3e-5], (n, 2))
+    shift = g.choice([0.0, 1.0, -1.0, 7.0, -3.0], (n, 2))
+    q = np.empty((n, 3), np.float32)
+    q[:, :2] = (k + eps + shift).astype(np.float32)
+    q[:, 2] = g.choice([0.0, -1.0, s_max, s_max + 2.0, 0.5, 1.0], n) + g.uniform(0, 1, n) * (g.random(n) < 0.5)
+    return q
+
+
+@pytest.mark.parametrize("res,levels", [(64, 7), (256, 9), ([(128, 32), (32, 128), (64, 64), (128, 128)], 6)])
+def test_gradients_on_cell_edges_and_wrapped_queries(bcf, res, levels):
+    """The scatter's LDS windows cover a cell's footprint; queries on the cell
+    edges, wrapped from far outside [0, 1) and clamped in LOD take the same
+    gradients as the oracle (bars as above)."""
+    g = synth.rng(451 + levels)
+    n_tex = 4
+    texs, dims, params, _, _ = problem(452 + levels, res=res, levels=levels, n=10, ste=True)
+    q = special_train_queries(g, 4000, levels - 1.0)
+    go = g.standard_normal((len(q), dims[-1])).astype(np.float32)
+    geo, ends, idxs, p = to_gpu(bcf, texs, dims, params, True)
+    g_end, g_idx, g_par = bcf.train_backward(geo, ends, idxs, p, dev(q), dev(go))
+    torch.cuda.synchronize()
+    _, r_end, r_idx, r_par = T.gradients(texs, dims, params, q, go, True)
+    for name, got, ref in [("params", g_par, r_par)] + \
+            [(f"endpoints[{t}]", g_end[t], r_end[t]) for t in range(n_tex)] + \
+            [(f"indices[{t}]", g_idx[t], r_idx[t]) for t in range(n_tex)]:
+        got = got.cpu().numpy().astype(np.float64)
+        scale = max(np.abs(ref).max(), 1e-30)
+        err = np.abs(got - ref).max() / scale
+        log(f"  res={res} {name}: max err {err:.2e} of max |grad| {scale:.3e}")
+        assert err <= 2e-4, name
+
+
+def test_backward_over_several_sort_batches_is_additive(bcf):
+    """More than 2^20 samples are sorted and scattered 2^20 at a time; the
+    gradient of the whole batch equals the sum of its two parts' gradients."""
+    texs, dims, params, q, go = problem(461, res=64, levels=7, n=(1 << 20) + 5000, ste=True)
+    geo, ends, idxs, p = to_gpu(bcf, texs, dims, params, True)
+    qd, gd = dev(q), dev(go)
+    whole = bcf.train_backward(geo, ends, idxs, p, qd, gd)
+    a = bcf.train_backward(geo, ends, idxs, p, qd[:1 << 20], gd[:1 << 20])
+    b = bcf.train_backward(geo, ends, idxs, p, qd[1 << 20:], gd[1 << 20:])
+    torch.cuda.synchronize()
+    def flat(r):
+        return [*r[0], *r[1], r[2]]
+    for w, x, y in zip(flat(whole), flat(a), flat(b)):
+        ref = (x + y).double()
+        err = float((w.double() - ref).abs().max() / max(float(ref.abs().max()), 1e-30))
+        log(f"  additive: max err {err:.2e}")
+        assert err <= 2e-4
