@@ -412,40 +412,76 @@ __global__ void __launch_bounds__(kTrainThreads) k_train_forward(TrainDesc d, co
     }
 }
 
-// Per-lane share of a layer's parameter gradients: entry e = lane + 64 k of
-// the layer's W (row-major) then b.
-constexpr int entries_per_lane(int n_in, int n_out) { return (n_out * (n_in + 1) + 63) / 64; }
+// A layer's parameter gradients, dL/dW[j][i] = sum over queries of
+// delta[q][j] * a[q][i], summed per wave on the matrix cores: 16 x 16 tiles
+// (rows j = 16 m + .., columns i = 16 n + ..) of fp32 16x16x4 MFMAs, K running
+// over the wave's 64 queries; at step s lane L supplies dl[4 s + L / 16][16 m
+// + L % 16] and a[4 s + L / 16][16 n + L % 16], and tile register k of lane L
+// holds row 4 (L / 16) + k, column L % 16. The bias gradients (sum over
+// queries of delta[q][j]) are the per-lane sums of the same dl reads, added
+// across the four lane groups when flushed.
+template <int MT, int NT>
+struct LayerGrad {
+    f32x4 w[MT][NT];
+    float b[MT];
+};
 
-// acc[k] += sum over the wave's 64 queries of delta[q][j] * a[q][i] for the
-// lane's entries; a[q][n_in] holds 1 for the bias entries.
-template <int K>
-__device__ __forceinline__ void accumulate(float acc[K], const float (*a)[kTrainMaxHidden + 1],
-                                           const float (*dl)[kTrainMaxHidden], uint32_t n_in, uint32_t n_out,
-                                           uint32_t lane)
+template <int MT, int NT>
+__device__ __forceinline__ void grad_zero(LayerGrad<MT, NT> &g)
 {
-    const uint32_t n_w = n_in * n_out;
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const uint32_t e = lane + 64u * (uint32_t)k;
-        if (e >= n_w + n_out) continue;
-        const uint32_t j = e < n_w ? e / n_in : e - n_w;
-        const uint32_t i = e < n_w ? e - j * n_in : n_in;
-        float s = 0.0f;
+    for (int m = 0; m < MT; ++m) {
+        g.b[m] = 0.0f;
+#pragma unroll
+        for (int n = 0; n < NT; ++n) g.w[m][n] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+    }
+}
+
+template <int MT, int NT>
+__device__ __forceinline__ void accumulate(LayerGrad<MT, NT> &g, const float (*a)[kTrainMaxHidden + 1],
+                                           const float (*dl)[kTrainMaxHidden], uint32_t lane)
+{
+    static_assert(16 * MT <= kTrainMaxHidden && 16 * NT <= kTrainMaxHidden, "tiles inside the LDS rows");
+    const uint32_t r = lane >> 4, c = lane & 15u;
 #pragma unroll 4
-        for (int q = 0; q < 64; ++q) s = fmaf(dl[q][j], a[q][i], s);
-        acc[k] += s;
+    for (uint32_t s = 0; s < 16; ++s) {
+        float av[NT], dv[MT];
+#pragma unroll
+        for (int n = 0; n < NT; ++n) av[n] = a[4 * s + r][16 * n + c];
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            dv[m] = dl[4 * s + r][16 * m + c];
+            g.b[m] += dv[m];
+        }
+#pragma unroll
+        for (int m = 0; m < MT; ++m)
+#pragma unroll
+            for (int n = 0; n < NT; ++n) g.w[m][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(dv[m], av[n], g.w[m][n], 0, 0, 0);
     }
 }
 
-template <int K>
-__device__ __forceinline__ void flush(const float acc[K], float *g, uint32_t n_in, uint32_t n_out, uint32_t lane)
+// Adds a wave's layer gradients to gw (W[n_out][n_in], row-major) and gb (b[n_out]).
+template <int MT, int NT>
+__device__ __forceinline__ void flush(const LayerGrad<MT, NT> &g, float *gw, float *gb, uint32_t n_in,
+                                      uint32_t n_out, uint32_t lane)
 {
+    const uint32_t r = lane >> 4, c = lane & 15u;
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const uint32_t e = lane + 64u * (uint32_t)k;
-        if (e < n_out * (n_in + 1u)) unsafeAtomicAdd(g + e, acc[k]);
+    for (int m = 0; m < MT; ++m) {
+#pragma unroll
+        for (int n = 0; n < NT; ++n)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t j = 16u * m + 4u * r + k, i = 16u * n + c;
+                if (j < n_out && i < n_in) unsafeAtomicAdd(gw + j * n_in + i, g.w[m][n][k]);
+            }
+        float b = g.b[m];
+        b += __shfl_xor(b, 16);
+        b += __shfl_xor(b, 32);
+        if (r == 0 && 16u * m + c < n_out) unsafeAtomicAdd(gb + 16u * m + c, b);
     }
 }
+
 
 // ---------------------------------------------------------------------------
 // the backward's sample order
@@ -536,9 +572,7 @@ template <int H, int NH>
 __global__ void __launch_bounds__(kBwdThreads, 2) k_train_backward(TrainDesc d, const float *queries, uint32_t n,
                                                                 const float *grad_out, const uint32_t *perm)
 {
-    constexpr int K0 = entries_per_lane(12, H);
-    constexpr int KH = entries_per_lane(H, H);
-    constexpr int KL = entries_per_lane(H, kMaxOut);
+    constexpr int T = H / 16;                 // 16-wide tiles of a hidden layer
     __shared__ float lds_a[kBwdWaves][64][kTrainMaxHidden + 1];
     __shared__ float lds_d[kBwdWaves][64][kTrainMaxHidden];
     __shared__ MlpLds<H, NH> mlp;
@@ -548,15 +582,14 @@ __global__ void __launch_bounds__(kBwdThreads, 2) k_train_backward(TrainDesc d, 
 
     const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
     const uint32_t n0 = d.dims[0], c = d.dims[NH + 1];
-    float acc0[K0], accH[NH > 1 ? NH - 1 : 1][KH], accL[KL];
+    // layer 0 (at most 12 inputs), the hidden layers, the output layer (at most 16 rows)
+    LayerGrad<T, 1> g0;
+    LayerGrad<T, T> gh[NH > 1 ? NH - 1 : 1];
+    LayerGrad<1, T> gl;
+    grad_zero(g0);
 #pragma unroll
-    for (int k = 0; k < K0; ++k) acc0[k] = 0.0f;
-#pragma unroll
-    for (int l = 0; l < (NH > 1 ? NH - 1 : 1); ++l)
-#pragma unroll
-        for (int k = 0; k < KH; ++k) accH[l][k] = 0.0f;
-#pragma unroll
-    for (int k = 0; k < KL; ++k) accL[k] = 0.0f;
+    for (int l = 0; l < (NH > 1 ? NH - 1 : 1); ++l) grad_zero(gh[l]);
+    grad_zero(gl);
 
     float (*a)[kTrainMaxHidden + 1] = lds_a[wv];
     float (*dl)[kTrainMaxHidden] = lds_d[wv];
@@ -588,7 +621,7 @@ __global__ void __launch_bounds__(kBwdThreads, 2) k_train_backward(TrainDesc d, 
 #pragma unroll
         for (int j = 0; j < kMaxOut; ++j) dl[lane][j] = delta[j];
         wave_sync_lds();
-        accumulate<KL>(accL, a, dl, H, c, lane);
+        accumulate(gl, a, dl, lane);
         wave_sync_lds();
         // back through the hidden layers: delta of hidden layer l's pre-activation
 #pragma unroll
@@ -636,8 +669,8 @@ __global__ void __launch_bounds__(kBwdThreads, 2) k_train_backward(TrainDesc d, 
 #pragma unroll
             for (int j = 0; j < H; ++j) dl[lane][j] = delta[j];
             wave_sync_lds();
-            if (l == 0) accumulate<K0>(acc0, a, dl, n0, H, lane);
-            else accumulate<KH>(accH[l > 0 ? l - 1 : 0], a, dl, H, H, lane);
+            if (l == 0) accumulate(g0, a, dl, lane);
+            else accumulate(gh[l > 0 ? l - 1 : 0], a, dl, lane);
             wave_sync_lds();
         }
         // dL/dz = W_0^T delta
@@ -660,23 +693,29 @@ __global__ void __launch_bounds__(kBwdThreads, 2) k_train_backward(TrainDesc d, 
             dst[2] = make_float4(dz[8], dz[9], dz[10], dz[11]);
         }
     }
-    flush<K0>(acc0, d.g_params + d.w_off[0], n0, H, lane);
+    flush(g0, d.g_params + d.w_off[0], d.g_params + d.b_off[0], n0, H, lane);
 #pragma unroll
-    for (int l = 1; l < NH; ++l) flush<KH>(accH[l - 1], d.g_params + d.w_off[l], H, H, lane);
-    flush<KL>(accL, d.g_params + d.w_off[NH], H, c, lane);
+    for (int l = 1; l < NH; ++l) flush(gh[l - 1], d.g_params + d.w_off[l], d.g_params + d.b_off[l], H, H, lane);
+    flush(gl, d.g_params + d.w_off[NH], d.g_params + d.b_off[NH], H, c, lane);
 }
 
 // ---------------------------------------------------------------------------
 // dL/dz -> dL/d texel
 
 constexpr int kScatterThreads = 256;
-constexpr uint32_t kWindowFloats = 8192;      // 32 KB of LDS windows per workgroup
+constexpr uint32_t kWindowFloats = 12288;     // 48 KB of LDS windows per workgroup
+// A window of at most kSmallWindow positions (a coarse level, where many of a
+// wave's samples add to the same few texels) is held kWindowCopies times, lane
+// L adding to copy L % kWindowCopies, so that fewer lanes of one atomic
+// instruction meet on one address; the copies are summed when flushed.
+constexpr uint32_t kSmallWindow = 16;
+constexpr uint32_t kWindowCopies = 8;
 
 // A window of one (pyramid, level): the texels x0 .. x0 + w - 1 (wrapped) of
-// rows y0 .. y0 + h - 1, three floats each from `off` in the pool; off = ~0u:
-// the level's gradients go straight to memory.
+// rows y0 .. y0 + h - 1, three floats each from `off` in the pool, `copies`
+// times over; off = ~0u: the level's gradients go straight to memory.
 struct TexWindow {
-    uint32_t x0, y0, w, h, off;
+    uint32_t x0, y0, w, h, off, copies;
 };
 
 // One workgroup per cell of the sample sort: the cell's samples (sorted
@@ -722,9 +761,10 @@ __global__ void __launch_bounds__(kScatterThreads) k_train_scatter(TrainDesc d, 
                 W.y0 = wh == hl ? 0u : (uint32_t)(int)fy & (hl - 1u);
                 W.w = ww;
                 W.h = wh;
-                if (used + 3u * ww * wh <= kWindowFloats) {
+                W.copies = ww * wh <= kSmallWindow ? kWindowCopies : 1u;
+                if (used + 3u * ww * wh * W.copies <= kWindowFloats) {
                     W.off = used;
-                    used += 3u * ww * wh;
+                    used += 3u * ww * wh * W.copies;
                 }
             }
         pool_used = used;
@@ -753,7 +793,8 @@ __global__ void __launch_bounds__(kScatterThreads) k_train_scatter(TrainDesc d, 
             const TexWindow W = win[t][l];
             const uint32_t dx = (x - W.x0) & (e.x - 1u), dy = (y - W.y0) & (e.y - 1u);
             if (W.off != ~0u && dx < W.w && dy < W.h) {
-                float *p = pool + W.off + 3u * (dy * W.w + dx);
+                const uint32_t copy = W.copies > 1u ? threadIdx.x % kWindowCopies : 0u;
+                float *p = pool + W.off + 3u * (copy * W.w * W.h + dy * W.w + dx);
                 atomicAdd(p + 0, wt[k] * dz[3 * t + 0]);
                 atomicAdd(p + 1, wt[k] * dz[3 * t + 1]);
                 atomicAdd(p + 2, wt[k] * dz[3 * t + 2]);
@@ -771,8 +812,10 @@ __global__ void __launch_bounds__(kScatterThreads) k_train_scatter(TrainDesc d, 
             const TexWindow W = win[t][l];
             if (W.off == ~0u) continue;
             const uint4 e = lut[t][l];
-            for (uint32_t i = threadIdx.x; i < 3u * W.w * W.h; i += kScatterThreads) {
-                const float v = pool[W.off + i];
+            const uint32_t size = 3u * W.w * W.h;
+            for (uint32_t i = threadIdx.x; i < size; i += kScatterThreads) {
+                float v = pool[W.off + i];
+                for (uint32_t k = 1; k < W.copies; ++k) v += pool[W.off + k * size + i];
                 if (v == 0.0f) continue;
                 const uint32_t p = i / 3u, c = i - 3u * p, dy = p / W.w, dx = p - dy * W.w;
                 const uint32_t x = (W.x0 + dx) & (e.x - 1u), y = (W.y0 + dy) & (e.y - 1u);
