@@ -7,7 +7,7 @@
 //   k_train_bin_*     the backward's samples sorted by position (counting
 //                     sort over a grid of cells on the wrapped (u, v))
 //   k_train_backward  queries, dL/dG -> dL/d features per sample and dL/d MLP
-//                     parameters (per-wave sums through LDS)
+//                     parameters (per-wave sums on the matrix cores)
 //   k_train_scatter   dL/d features -> dL/d texel, one workgroup per cell:
 //                     sums in LDS windows over the cell's footprint, then
 //                     one float atomic per touched texel channel
