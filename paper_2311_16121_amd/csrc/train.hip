@@ -32,10 +32,6 @@ namespace {
 
 constexpr float kA = 31.0f / 64.0f;      // a of eq. (6) for the unsigned format
 constexpr int kTrainThreads = 256;
-// the backward runs three waves per workgroup: its LDS (per-wave reduction
-// buffers, the MLP and the level table, ≈ 60 KB) then fits two workgroups per CU
-constexpr int kBwdThreads = 192;
-constexpr int kBwdWaves = kBwdThreads / 64;
 
 __global__ void __launch_bounds__(256) k_train_zero(float *p, uint32_t n)
 {
@@ -228,10 +224,37 @@ __device__ __forceinline__ void load_level_lut(const TrainDesc &d, TrainLevelLut
     }
 }
 
+// The four bilinear taps of wrapped (uf, vf) on one level (e = its LUT entry:
+// width, height, first texel) and their weights times the level weight lw:
+// columns xa, xb = xa + 1 and rows ya, yb = ya + 1 (wrapped); w[] in the order
+// (ya, xa), (ya, xb), (yb, xa), (yb, xb).
+struct LevelTaps {
+    uint32_t xa, xb, ya, yb;
+    float w[4];
+};
+
+__device__ __forceinline__ LevelTaps level_taps(uint4 e, float uf, float vf, float lw)
+{
+    LevelTaps r;
+    const uint32_t wl = e.x, hl = e.y;
+    const float x = fmaf(uf, (float)wl, -0.5f), y = fmaf(vf, (float)hl, -0.5f);
+    const float x0 = floorf(x), y0 = floorf(y);
+    const float fx = x - x0, fy = y - y0;
+    r.xa = (uint32_t)(int)x0 & (wl - 1u);
+    r.xb = (r.xa + 1u) & (wl - 1u);
+    r.ya = (uint32_t)(int)y0 & (hl - 1u);
+    r.yb = (r.ya + 1u) & (hl - 1u);
+    r.w[0] = lw * (1.0f - fx) * (1.0f - fy);
+    r.w[1] = lw * fx * (1.0f - fy);
+    r.w[2] = lw * (1.0f - fx) * fy;
+    r.w[3] = lw * fx * fy;
+    return r;
+}
+
 // The 32 taps of a query (4 pyramids x 2 levels x 4 texels): texel index and
 // weight (bilinear times trilinear); pyramids past n_tex get weight 0.
 __device__ __forceinline__ void taps(const TrainDesc &d, const TrainLevelLut &lut, float u, float v, float s,
-                                     uint32_t idx[32], float wt[32], uint32_t lvl[8] = nullptr)
+                                     uint32_t idx[32], float wt[32])
 {
     const float uf = u - floorf(u), vf = v - floorf(v);          // wrap addressing
 #pragma unroll
@@ -247,24 +270,16 @@ __device__ __forceinline__ void taps(const TrainDesc &d, const TrainLevelLut &lu
         for (int k = 0; k < 2; ++k) {
             const uint32_t l = k ? l1 : l0;
             const float lw = on * (k ? lam : 1.0f - lam);
-            if (lvl) lvl[2 * ti + k] = l;
             const uint4 e = lut[slot][l];
-            const uint32_t wl = e.x, hl = e.y;
-            const float x = fmaf(uf, (float)wl, -0.5f), y = fmaf(vf, (float)hl, -0.5f);
-            const float x0 = floorf(x), y0 = floorf(y);
-            const float fx = x - x0, fy = y - y0;
-            const uint32_t xa = (uint32_t)(int)x0 & (wl - 1u), xb = (xa + 1u) & (wl - 1u);
-            const uint32_t ya = (uint32_t)(int)y0 & (hl - 1u), yb = (ya + 1u) & (hl - 1u);
-            const uint32_t base = e.z;
+            const LevelTaps lt = level_taps(e, uf, vf, lw);
+            const uint32_t wl = e.x, base = e.z;
             const int o = 8 * ti + 4 * k;
-            idx[o + 0] = base + ya * wl + xa;
-            idx[o + 1] = base + ya * wl + xb;
-            idx[o + 2] = base + yb * wl + xa;
-            idx[o + 3] = base + yb * wl + xb;
-            wt[o + 0] = lw * (1.0f - fx) * (1.0f - fy);
-            wt[o + 1] = lw * fx * (1.0f - fy);
-            wt[o + 2] = lw * (1.0f - fx) * fy;
-            wt[o + 3] = lw * fx * fy;
+            idx[o + 0] = base + lt.ya * wl + lt.xa;
+            idx[o + 1] = base + lt.ya * wl + lt.xb;
+            idx[o + 2] = base + lt.yb * wl + lt.xa;
+            idx[o + 3] = base + lt.yb * wl + lt.xb;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) wt[o + i] = lt.w[i];
         }
     }
 }
@@ -568,11 +583,23 @@ __global__ void __launch_bounds__(kBinThreads) k_train_bin_scatter(const float *
     if (i < n) perm[hist[bin] + rank] = i;
 }
 
+// Waves per workgroup of the backward: four when its LDS (per-wave rows for
+// the parameter-gradient products, the MLP, the level table) lets two
+// workgroups share a CU -- two waves per SIMD, as its registers allow --
+// else three.
 template <int H, int NH>
-__global__ void __launch_bounds__(kBwdThreads, 2) k_train_backward(TrainDesc d, const float *queries, uint32_t n,
+constexpr int bwd_waves()
+{
+    constexpr int rows = 64 * (2 * kTrainMaxHidden + 1) * 4;
+    return 4 * rows + (int)sizeof(MlpLds<H, NH>) + (int)sizeof(TrainLevelLut) <= 80 * 1024 ? 4 : 3;
+}
+
+template <int H, int NH>
+__global__ void __launch_bounds__((64 * bwd_waves<H, NH>()), 2) k_train_backward(TrainDesc d, const float *queries, uint32_t n,
                                                                 const float *grad_out, const uint32_t *perm)
 {
     constexpr int T = H / 16;                 // 16-wide tiles of a hidden layer
+    constexpr int kBwdWaves = bwd_waves<H, NH>();
     __shared__ float lds_a[kBwdWaves][64][kTrainMaxHidden + 1];
     __shared__ float lds_d[kBwdWaves][64][kTrainMaxHidden];
     __shared__ MlpLds<H, NH> mlp;
@@ -703,19 +730,14 @@ __global__ void __launch_bounds__(kBwdThreads, 2) k_train_backward(TrainDesc d, 
 // dL/dz -> dL/d texel
 
 constexpr int kScatterThreads = 256;
-constexpr uint32_t kWindowFloats = 12288;     // 48 KB of LDS windows per workgroup
-// A window of at most kSmallWindow positions (a coarse level, where many of a
-// wave's samples add to the same few texels) is held kWindowCopies times, lane
-// L adding to copy L % kWindowCopies, so that fewer lanes of one atomic
-// instruction meet on one address; the copies are summed when flushed.
-constexpr uint32_t kSmallWindow = 16;
-constexpr uint32_t kWindowCopies = 8;
+constexpr uint32_t kWindowFloats = 8192;      // 32 KB of LDS windows per workgroup
 
 // A window of one (pyramid, level): the texels x0 .. x0 + w - 1 (wrapped) of
-// rows y0 .. y0 + h - 1, three floats each from `off` in the pool, `copies`
-// times over; off = ~0u: the level's gradients go straight to memory.
+// rows y0 .. y0 + h - 1, three floats each from `off` in the pool; off = ~0u:
+// the level's gradients go straight to memory. div_w = ceil(2^32 / w) (w > 1),
+// so that p / w = umulhi(p, div_w) for the pool's positions p (p < 2^13).
 struct TexWindow {
-    uint32_t x0, y0, w, h, off, copies;
+    uint32_t x0, y0, w, h, off, div_w;
 };
 
 // One workgroup per cell of the sample sort: the cell's samples (sorted
@@ -736,7 +758,11 @@ __global__ void __launch_bounds__(kScatterThreads) k_train_scatter(TrainDesc d, 
     if (begin == end) return;                          // uniform over the workgroup
     load_level_lut(d, lut);
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < 64u) {
+        // lane i: window i of the allocation order, the coarsest levels first
+        // (level 15 - i / 4, pyramid i % 4); the pool goes to a prefix of it
+        const uint32_t i = threadIdx.x, l = kMaxLevels - 1u - i / kMaxTextures, t = i % kMaxTextures;
+        static_assert(kMaxLevels * kMaxTextures == 64, "one lane per window");
         // the cell's corner from its Z-order number
         uint32_t cx = 0, cy = 0;
 #pragma unroll
@@ -744,30 +770,36 @@ __global__ void __launch_bounds__(kScatterThreads) k_train_scatter(TrainDesc d, 
             cx |= ((cell >> (2 * b)) & 1u) << b;
             cy |= ((cell >> (2 * b + 1)) & 1u) << b;
         }
-        uint32_t used = 0;
-        for (int l = kMaxLevels - 1; l >= 0; --l)
-            for (uint32_t t = 0; t < (uint32_t)kMaxTextures; ++t) {
-                TexWindow &W = win[t][l];
-                W.off = ~0u;
-                if (t >= d.n_tex || (uint32_t)l >= d.tex[t].levels) continue;
-                // a cell spans wl / side texels; its samples' taps span at
-                // most ceil of that + 2 columns from floor(cx wl / side - 0.5)
-                const uint32_t wl = lut[t][l].x, hl = lut[t][l].y;
-                const uint32_t ww = min(wl, (wl + kTrainBinSide - 1) / kTrainBinSide + 2u);
-                const uint32_t wh = min(hl, (hl + kTrainBinSide - 1) / kTrainBinSide + 2u);
-                const float fx = floorf((float)cx * ((float)wl / (float)kTrainBinSide) - 0.5f);
-                const float fy = floorf((float)cy * ((float)hl / (float)kTrainBinSide) - 0.5f);
-                W.x0 = ww == wl ? 0u : (uint32_t)(int)fx & (wl - 1u);
-                W.y0 = wh == hl ? 0u : (uint32_t)(int)fy & (hl - 1u);
-                W.w = ww;
-                W.h = wh;
-                W.copies = ww * wh <= kSmallWindow ? kWindowCopies : 1u;
-                if (used + 3u * ww * wh * W.copies <= kWindowFloats) {
-                    W.off = used;
-                    used += 3u * ww * wh * W.copies;
-                }
-            }
-        pool_used = used;
+        const uint32_t levels_t = t == 0 ? d.tex[0].levels : t == 1 ? d.tex[1].levels
+                                : t == 2 ? d.tex[2].levels : d.tex[3].levels;
+        const bool have = t < d.n_tex && l < levels_t;
+        // a cell spans wl / side texels; its samples' taps span at most ceil
+        // of that + 2 columns from floor(cx wl / side - 0.5)
+        const uint32_t wl = lut[t][l].x, hl = lut[t][l].y;
+        const uint32_t ww = min(wl, (wl + kTrainBinSide - 1) / kTrainBinSide + 2u);
+        const uint32_t wh = min(hl, (hl + kTrainBinSide - 1) / kTrainBinSide + 2u);
+        const uint32_t size = have ? 3u * ww * wh : 0u;
+        uint32_t upto = size;                      // inclusive prefix over the order
+#pragma unroll
+        for (uint32_t k = 1; k < 64; k <<= 1) {
+            const uint32_t o = __shfl_up(upto, k);
+            if (i >= k) upto += o;
+        }
+        const float fx = floorf((float)cx * ((float)wl / (float)kTrainBinSide) - 0.5f);
+        const float fy = floorf((float)cy * ((float)hl / (float)kTrainBinSide) - 0.5f);
+        TexWindow W;
+        W.x0 = ww == wl ? 0u : (uint32_t)(int)fx & (wl - 1u);
+        W.y0 = wh == hl ? 0u : (uint32_t)(int)fy & (hl - 1u);
+        W.w = ww;
+        W.h = wh;
+        W.off = have && upto <= kWindowFloats ? upto - size : ~0u;
+        W.div_w = ww > 1u ? 0xFFFFFFFFu / ww + 1u : 0u;
+        win[t][l] = W;
+        // the pool in use: the end of the last window that fits
+        uint32_t in_use = upto <= kWindowFloats ? upto : 0u;
+#pragma unroll
+        for (uint32_t k = 1; k < 64; k <<= 1) in_use = max(in_use, __shfl_xor(in_use, k));
+        if (i == 0u) pool_used = in_use;
     }
     __syncthreads();
     const uint32_t used = pool_used;
@@ -778,31 +810,47 @@ __global__ void __launch_bounds__(kScatterThreads) k_train_scatter(TrainDesc d, 
         const float4 *src = reinterpret_cast<const float4 *>(d.bin_dz + 12u * (size_t)j);
         const float4 z0 = src[0], z1 = src[1], z2 = src[2];
         const float dz[12] = {z0.x, z0.y, z0.z, z0.w, z1.x, z1.y, z1.z, z1.w, z2.x, z2.y, z2.z, z2.w};
-        uint32_t idx[32], lvl[8];
-        float wt[32];
-        taps(d, lut, queries[3u * q], queries[3u * q + 1u], queries[3u * q + 2u], idx, wt, lvl);
+        const float u = queries[3u * q], v = queries[3u * q + 1u], s = queries[3u * q + 2u];
+        const float uf = u - floorf(u), vf = v - floorf(v);       // wrap addressing
 #pragma unroll
-        for (int k = 0; k < 32; ++k) {
-            const int t = k / 8;
-            // a zero weight (an unused second level, a pyramid past n_tex) adds nothing
-            if (t >= (int)d.n_tex || wt[k] == 0.0f) continue;
-            const uint32_t l = lvl[k / 4];
-            const uint4 e = lut[t][l];
-            const uint32_t rel = idx[k] - e.z;             // y * wl + x, wl a power of two
-            const uint32_t x = rel & (e.x - 1u), y = rel >> __builtin_ctz(e.x);
-            const TexWindow W = win[t][l];
-            const uint32_t dx = (x - W.x0) & (e.x - 1u), dy = (y - W.y0) & (e.y - 1u);
-            if (W.off != ~0u && dx < W.w && dy < W.h) {
-                const uint32_t copy = W.copies > 1u ? threadIdx.x % kWindowCopies : 0u;
-                float *p = pool + W.off + 3u * (copy * W.w * W.h + dy * W.w + dx);
-                atomicAdd(p + 0, wt[k] * dz[3 * t + 0]);
-                atomicAdd(p + 1, wt[k] * dz[3 * t + 1]);
-                atomicAdd(p + 2, wt[k] * dz[3 * t + 2]);
-            } else {
-                float *gp = reinterpret_cast<float *>(d.g_texels + idx[k]);
-                unsafeAtomicAdd(gp + 0, wt[k] * dz[3 * t + 0]);
-                unsafeAtomicAdd(gp + 1, wt[k] * dz[3 * t + 1]);
-                unsafeAtomicAdd(gp + 2, wt[k] * dz[3 * t + 2]);
+        for (int t = 0; t < kMaxTextures; ++t) {
+            if (t >= (int)d.n_tex) break;
+            // the two levels of eq. (10) as the forward takes them
+            const TrainTexDesc &tx = d.tex[t];
+            const float si = fminf(fmaxf(s + tx.bias, 0.0f), (float)(tx.levels - 1));   // NaN -> 0
+            const uint32_t l0 = (uint32_t)floorf(si);
+            const uint32_t l1 = min(l0 + 1u, tx.levels - 1u);
+            const float lam = si - (float)l0;
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const uint32_t l = k ? l1 : l0;
+                const float lw = k ? lam : 1.0f - lam;
+                // a zero weight (an unused second level) adds nothing
+                if (lw == 0.0f) continue;
+                const uint4 e = lut[t][l];
+                const LevelTaps lt = level_taps(e, uf, vf, lw);
+                const TexWindow W = win[t][l];
+                const uint32_t dxa = (lt.xa - W.x0) & (e.x - 1u), dxb = (lt.xb - W.x0) & (e.x - 1u);
+                const uint32_t dya = (lt.ya - W.y0) & (e.y - 1u), dyb = (lt.yb - W.y0) & (e.y - 1u);
+                const uint32_t base = W.off;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float wt = lt.w[i];
+                    if (wt == 0.0f) continue;
+                    const uint32_t x = i & 1 ? lt.xb : lt.xa, y = i & 2 ? lt.yb : lt.ya;
+                    const uint32_t dx = i & 1 ? dxb : dxa, dy = i & 2 ? dyb : dya;
+                    if (W.off != ~0u && dx < W.w && dy < W.h) {
+                        float *p = pool + base + 3u * (__umul24(dy, W.w) + dx);
+                        atomicAdd(p + 0, wt * dz[3 * t + 0]);
+                        atomicAdd(p + 1, wt * dz[3 * t + 1]);
+                        atomicAdd(p + 2, wt * dz[3 * t + 2]);
+                    } else {
+                        float *gp = reinterpret_cast<float *>(d.g_texels + e.z + y * e.x + x);
+                        unsafeAtomicAdd(gp + 0, wt * dz[3 * t + 0]);
+                        unsafeAtomicAdd(gp + 1, wt * dz[3 * t + 1]);
+                        unsafeAtomicAdd(gp + 2, wt * dz[3 * t + 2]);
+                    }
+                }
             }
         }
     }
@@ -814,10 +862,9 @@ __global__ void __launch_bounds__(kScatterThreads) k_train_scatter(TrainDesc d, 
             const uint4 e = lut[t][l];
             const uint32_t size = 3u * W.w * W.h;
             for (uint32_t i = threadIdx.x; i < size; i += kScatterThreads) {
-                float v = pool[W.off + i];
-                for (uint32_t k = 1; k < W.copies; ++k) v += pool[W.off + k * size + i];
+                const float v = pool[W.off + i];
                 if (v == 0.0f) continue;
-                const uint32_t p = i / 3u, c = i - 3u * p, dy = p / W.w, dx = p - dy * W.w;
+                const uint32_t p = i / 3u, c = i - 3u * p, dy = W.w > 1u ? __umulhi(p, W.div_w) : p, dx = p - dy * W.w;
                 const uint32_t x = (W.x0 + dx) & (e.x - 1u), y = (W.y0 + dy) & (e.y - 1u);
                 unsafeAtomicAdd(reinterpret_cast<float *>(d.g_texels + e.z + y * e.x + x) + c, v);
             }
@@ -850,8 +897,9 @@ hipError_t backward_hn(const TrainDesc &d, const float *queries, uint32_t n, con
 {
     // a few workgroups per CU (each flushes its parameter and small-level
     // sums once), a multiple of the 8 XCDs
-    const unsigned grid = (grid_for((n + 63u) / 64u, kBwdWaves, 768) + 7u) & ~7u;
-    k_train_backward<H, NH><<<grid, kBwdThreads, 0, s>>>(d, queries, n, grad_out, d.bin_perm);
+    constexpr int waves = bwd_waves<H, NH>();
+    const unsigned grid = (grid_for((n + 63u) / 64u, waves, 768) + 7u) & ~7u;
+    k_train_backward<H, NH><<<grid, 64 * waves, 0, s>>>(d, queries, n, grad_out, d.bin_perm);
     return hipGetLastError();
 }
 
