@@ -114,12 +114,12 @@ __device__ __forceinline__ TexelSite texel_site(const TrainDesc &d, uint32_t gb,
     uint32_t l = 0;
     while (l + 1 < tx.levels && b >= tx.blk_off[l + 1]) ++l;
     const uint32_t wl = max(tx.w >> l, 1u), hl = max(tx.h >> l, 1u);
-    const uint32_t bxn = (wl + 3u) >> 2;
+    const uint32_t bxn = (wl + 3u) >> 2;          // a power of two, as the level width is
     const uint32_t lb = b - tx.blk_off[l];
     s.ti = ti;
     s.b = b;
-    s.x = (lb % bxn) * 4u + (t & 3u);
-    s.y = (lb / bxn) * 4u + (t >> 2);
+    s.x = (lb & (bxn - 1u)) * 4u + (t & 3u);
+    s.y = (lb >> __builtin_ctz(bxn)) * 4u + (t >> 2);
     s.valid = s.x < wl && s.y < hl;
     s.tex = tx.tex_off[l] + s.y * wl + s.x;
     return s;
@@ -148,6 +148,25 @@ __global__ void __launch_bounds__(kTrainThreads) k_train_texels(TrainDesc d)
         for (int c = 0; c < 3; ++c) w[c] = texel_chan<STE>(e[6u * sub + c], e[6u * sub + 3u + c], x).w;
         d.texels[s.tex] = make_float4(w[0], w[1], w[2], 0.0f);
     }
+}
+
+// Sum over the 16 lanes of a DPP row (a block's texels), in every lane of the
+// row: lanes paired by XOR 1, then 2, then the row's two quads of each half,
+// then its two halves -- the order of a shuffle butterfly over XOR 1, 2, 4, 8,
+// with DPP moves instead of LDS permutes.
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float x)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ float row16_sum(float v)
+{
+    v += dpp_move<0xB1>(v);       // quad_perm [1, 0, 3, 2]
+    v += dpp_move<0x4E>(v);       // quad_perm [2, 3, 0, 1]
+    v += dpp_move<0x141>(v);      // row_half_mirror: lane i of a half row takes lane 7 - i
+    v += dpp_move<0x140>(v);      // row_mirror: lane i takes lane 15 - i
+    return v;
 }
 
 template <bool STE>
@@ -191,8 +210,7 @@ __global__ void __launch_bounds__(kTrainThreads) k_train_blocks(TrainDesc d)
         for (int j = 0; j < 4; ++j)
 #pragma unroll
             for (int c = 0; c < 3; ++c)
-#pragma unroll
-                for (int m = 1; m < 16; m <<= 1) sum[j][c] += __shfl_xor(sum[j][c], m, 16);
+                sum[j][c] = row16_sum(sum[j][c]);
         if (t < 12) {
             float v = 0.0f;
 #pragma unroll
