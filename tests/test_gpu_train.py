@@ -274,3 +274,28 @@ def test_backward_over_several_sort_batches_is_additive(bcf):
         err = float((w.double() - ref).abs().max() / max(float(ref.abs().max()), 1e-30))
         log(f"  additive: max err {err:.2e}")
         assert err <= 2e-4
+
+
+def test_gradients_when_the_scatter_windows_overflow(bcf):
+    """Two 2048^2 pyramids: the scatter's LDS windows of a cell hold every level
+    of the first pyramid but not level 0 of the second, whose taps then go
+    straight to memory; the gradients still match the oracle (bars as above)."""
+    texs, dims, params, q, go = problem(471, res=2048, levels=12, n=1 << 18, dims=(6, 16, 16, 4), ste=True,
+                                        n_tex=2)
+    geo, ends, idxs, p = to_gpu(bcf, texs, dims, params, True)
+    g_end, g_idx, g_par = bcf.train_backward(geo, ends, idxs, p, dev(q), dev(go))
+    torch.cuda.synchronize()
+    _, r_end, r_idx, r_par = T.gradients(texs, dims, params, q, go, True)
+    gp = g_par.cpu().numpy().astype(np.float64)
+    assert np.abs(gp - r_par).max() <= 2e-4 * np.abs(r_par).max(), "params"
+    # per level: level 0's gradients are far smaller than the coarse levels'
+    for t, tex in enumerate(texs):
+        ge = g_end[t].cpu().numpy().astype(np.float64)
+        gi = g_idx[t].cpu().numpy().astype(np.float64)
+        for level, (first, bx, by, _, _) in enumerate(tex.level_blocks()):
+            sl = slice(first, first + bx * by)
+            for name, a, b in (("endpoints", ge[sl], r_end[t][sl]), ("indices", gi[sl], r_idx[t][sl])):
+                scale = np.abs(b).max()
+                err = np.abs(a - b).max() / scale if scale > 0 else np.abs(a).max()
+                assert err <= 2e-4, (t, level, name, err, scale)
+        log(f"  2 x 2048^2 pyramid {t}: block gradients within 2e-4 of each level's max |grad|")
