@@ -328,7 +328,8 @@ typedef struct {
 /* Device workspace bytes (256-byte aligned start) for the training calls
  * on this material: two texel images of 16 bytes per texel, then 52 MiB +
  * 32 KiB in which the backward sorts its samples by position and keeps
- * dL/d feature per sample (2^20 samples at a time). */
+ * dL/d feature per sample (2^20 samples at a time), then the forward's MLP
+ * operands in the matrix-core layout (a few KiB). */
 bcf_status bcf_train_workspace_size(const bcf_train_material *m, size_t *ws_bytes);
 
 /* G(u, v, s) for n queries (device [n][3]) into out (device [n][dims[n_layers]]),

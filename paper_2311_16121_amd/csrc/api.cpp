@@ -430,8 +430,16 @@ bcf_status describe_train(const bcf_train_material *m, bcf::TrainDesc *d, size_t
     }
     d->dims[m->n_layers] = out;
     d->n_params = off;
-    *ws_bytes = 2 * align_up(texels * 16, 256) + align_up((size_t)bcf::kTrainBinBatch * 4, 256) +
-                2 * align_up((size_t)bcf::kTrainBins * 4, 256) + (size_t)bcf::kTrainBinBatch * 48;
+    bcf::MlpShape &sh = d->ops_shape;
+    sh.n_layers = m->n_layers;
+    sh.n_hidden = m->n_layers - 1;
+    sh.hidden = hidden;
+    sh.out = out;
+    for (uint32_t l = 0; l <= m->n_layers; ++l) sh.dims[l] = m->dims[l];
+    const size_t sort_end = 2 * align_up(texels * 16, 256) + align_up((size_t)bcf::kTrainBinBatch * 4, 256) +
+                            2 * align_up((size_t)bcf::kTrainBins * 4, 256) + (size_t)bcf::kTrainBinBatch * 48;
+    d->ops = weights_layout(sh, bcf::MLP_MFMA_F32, align_up(sort_end, 256));
+    *ws_bytes = d->ops.total;
     return BCF_OK;
 }
 
@@ -452,6 +460,7 @@ bcf_status bind_train_ws(bcf::TrainDesc *d, void *ws)
     d->bin_next = reinterpret_cast<uint32_t *>(p);
     p += align_up((size_t)bcf::kTrainBins * 4, 256);
     d->bin_dz = reinterpret_cast<float *>(p);
+    d->ops_ws = static_cast<uint8_t *>(ws);
     return BCF_OK;
 }
 

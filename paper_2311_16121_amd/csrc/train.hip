@@ -3,7 +3,8 @@
 // and 10) and the ReLU MLP (eq. 3).
 //
 //   k_train_texels    block parameters -> texel images (r, g, b, 0) per level
-//   k_train_forward   queries -> G(u, v, s), one lane per query
+//   k_train_forward_mfma  queries -> G(u, v, s), one lane per query, the MLP
+//                     on the matrix cores
 //   k_train_bin_*     the backward's samples sorted by position (counting
 //                     sort over a grid of cells on the wrapped (u, v))
 //   k_train_backward  queries, dL/dG -> dL/d features per sample and dL/d MLP
@@ -25,6 +26,7 @@
 #include <algorithm>
 
 #include "bc6h_device.hpp"
+#include "frame_kernels.hpp"
 #include "train.hpp"
 
 namespace bcf {
@@ -426,22 +428,36 @@ __device__ __forceinline__ void mlp_forward(const MlpLds<H, NH> &m, uint32_t c, 
     }
 }
 
+// The forward with the MLP on the matrix cores (fp32 16x16x4 MFMAs, the
+// decode kernels' operand layout, prepared from the parameters per call): a
+// wave's 64 queries' features pass through LDS into the MFMA B layout, the
+// outputs come back through LDS to each query's lane.
 template <int H, int NH>
-__global__ void __launch_bounds__(kTrainThreads) k_train_forward(TrainDesc d, const float *queries, uint32_t n,
-                                                                 float *out)
+__global__ void __launch_bounds__(kTrainThreads) k_train_forward_mfma(TrainDesc d, const float *queries, uint32_t n,
+                                                                      float *out)
 {
-    __shared__ MlpLds<H, NH> mlp;
+    constexpr int kWaves = kTrainThreads / 64;
     __shared__ TrainLevelLut lut;
+    __shared__ float4_t stage[kWaves][64 * kMaxOut / 4];     // features, then output rows
     load_level_lut(d, lut);
-    load_mlp<H, NH>(d, mlp);                  // synchronises, also for `lut`
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63u, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t c = d.dims[NH + 1];
-    for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
-        float z[12], act[NH][H], o[kMaxOut];
-        features(d, lut, queries[3u * q], queries[3u * q + 1u], queries[3u * q + 2u], z);
-        mlp_forward<H, NH>(mlp, c, z, act, o);
-#pragma unroll
-        for (int j = 0; j < kMaxOut; ++j)
-            if ((uint32_t)j < c) out[(size_t)q * c + j] = o[j];
+    MfmaMlp<MLP_MFMA_F32, H, NH> mlp;
+    mlp.load(d.ops_ws, d.ops, lane);
+    float *st = reinterpret_cast<float *>(&stage[wv][0]);
+    float4_t (*feats)[4] = reinterpret_cast<float4_t (*)[4]>(&stage[wv][0]);
+    const uint32_t n_chunks = (n + 63u) / 64u;
+    for (uint32_t ch = blockIdx.x * kWaves + wv; ch < n_chunks; ch += gridDim.x * kWaves) {
+        const uint32_t q = ch * 64u + lane;
+        const bool live = q < n;
+        float z[12];
+        features(d, lut, live ? queries[3u * q] : 0.0f, live ? queries[3u * q + 1u] : 0.0f,
+                 live ? queries[3u * q + 2u] : 0.0f, z);
+        mlp_stage<MLP_MFMA_F32, H, NH, kMaxOut>(z, d.ops_ws, d.ops, mlp, feats, st, c, lane);
+        if (live)
+            for (uint32_t j = 0; j < c; ++j) out[(size_t)q * c + j] = st[lane * c + j];
+        wave_lds_sync();                              // the stage is rewritten by the next chunk
     }
 }
 
@@ -906,7 +922,9 @@ hipError_t launch_texels(const TrainDesc &d, hipStream_t s)
 template <int H, int NH>
 hipError_t forward_hn(const TrainDesc &d, const float *queries, uint32_t n, float *out, hipStream_t s)
 {
-    k_train_forward<H, NH><<<grid_for(n, kTrainThreads, 8192), kTrainThreads, 0, s>>>(d, queries, n, out);
+    hipError_t e = launch_prepare_weights(d.params, nullptr, d.ops_shape, MLP_MFMA_F32, d.ops, d.ops_ws, nullptr, s);
+    if (e != hipSuccess) return e;
+    k_train_forward_mfma<H, NH><<<grid_for(n, kTrainThreads, 8192), kTrainThreads, 0, s>>>(d, queries, n, out);
     return hipGetLastError();
 }
 

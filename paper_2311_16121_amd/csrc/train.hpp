@@ -48,6 +48,11 @@ struct TrainDesc {
     uint32_t dims[5];
     uint32_t n_layers;
     uint32_t w_off[4], b_off[4];   // float offsets of each layer's W and b in params
+    // the forward's MLP operands (workspace): the matrix-core layout of the
+    // fp32 16x16x4 MFMAs, offsets from ops_ws
+    MlpShape ops_shape;
+    WsLayout ops;
+    uint8_t *ops_ws;
     // the backward's sample sort (workspace): sorted sample indices, per-cell
     // counts, per-cell next free slot (after the sort: the end of the cell's
     // run), and dL/dz (12 floats) per sorted sample
