@@ -388,10 +388,11 @@ __device__ __forceinline__ void load_mlp(const TrainDesc &d, MlpLds<H, NH> &m)
     __syncthreads();
 }
 
-// Forward MLP with the hidden activations kept (act[l] = output of hidden layer l).
+// The MLP's hidden layers (act[l] = output of hidden layer l), as the
+// backward needs them; the output layer's values are not (its gradient is
+// the caller's dL/dG).
 template <int H, int NH>
-__device__ __forceinline__ void mlp_forward(const MlpLds<H, NH> &m, uint32_t c, const float z[12], float act[NH][H],
-                                            float out[kMaxOut])
+__device__ __forceinline__ void mlp_hidden(const MlpLds<H, NH> &m, const float z[12], float act[NH][H])
 {
     // inputs past dims[0] are zero (their weights are zero too)
 #pragma unroll
@@ -414,18 +415,6 @@ __device__ __forceinline__ void mlp_forward(const MlpLds<H, NH> &m, uint32_t c, 
             for (int i = 0; i < H; ++i) acc = fmaf(w[i], act[l - 1][i], acc);
             act[l][j] = fmaxf(acc, 0.0f);
         }
-#pragma unroll
-    for (int j = 0; j < kMaxOut; ++j) {
-        float acc = 0.0f;
-        if ((uint32_t)j < c) {
-            float w[H + 1];
-            lds_row<H>(m.wl[j], j ? out[j - 1] : act[NH - 1][H - 1], w);
-            acc = w[H];
-#pragma unroll
-            for (int i = 0; i < H; ++i) acc = fmaf(w[i], act[NH - 1][i], acc);
-        }
-        out[j] = acc;
-    }
 }
 
 // The forward with the MLP on the matrix cores (fp32 16x16x4 MFMAs, the
@@ -667,9 +656,9 @@ __global__ void __launch_bounds__((64 * bwd_waves<H, NH>()), 2) k_train_backward
         const float u = live ? queries[3u * q] : 0.0f;
         const float v = live ? queries[3u * q + 1u] : 0.0f;
         const float s = live ? queries[3u * q + 2u] : 0.0f;
-        float z[12], act[NH][H], o[kMaxOut];
+        float z[12], act[NH][H];
         features(d, lut, u, v, s, z);
-        mlp_forward<H, NH>(mlp, c, z, act, o);
+        mlp_hidden<H, NH>(mlp, z, act);
         float delta[kTrainMaxHidden];
 #pragma unroll
         for (int j = 0; j < kTrainMaxHidden; ++j)
