@@ -364,7 +364,8 @@ def bench_train(args):
     leaves = [torch.from_numpy(e).cuda().requires_grad_(True) for e in ends] + \
              [torch.from_numpy(x).cuda().requires_grad_(True) for x in idxs]
     w = torch.from_numpy(params).cuda().requires_grad_(True)
-    opt = torch.optim.Adam([{"params": leaves, "lr": 0.02}, {"params": [w], "lr": 2e-3}])
+    # torch's fused Adam: one kernel per step for every parameter tensor
+    opt = torch.optim.Adam([{"params": leaves, "lr": 0.02}, {"params": [w], "lr": 2e-3}], fused=True)
 
     def step():
         out = bcf.train_decode(geo, leaves[:4], leaves[4:], w, qd)
