@@ -10,8 +10,8 @@
 //   k_train_backward  queries, dL/dG -> dL/d features per sample and dL/d MLP
 //                     parameters (per-wave sums on the matrix cores)
 //   k_train_scatter   dL/d features -> dL/d texel, one workgroup per cell:
-//                     sums in LDS windows over the cell's footprint, then
-//                     one float atomic per touched texel channel
+//                     fixed-point sums in LDS windows over the cell's
+//                     footprint, then one float atomic per touched texel channel
 //   k_train_blocks    dL/d texel -> dL/d endpoints, dL/d indices (one lane
 //                     per texel, sums over a block's 16 lanes by shuffles)
 //
@@ -775,7 +775,7 @@ __global__ void __launch_bounds__(kScatterThreads) k_train_scatter(TrainDesc d, 
     __shared__ float pool[kWindowFloats];
     __shared__ TexWindow win[kMaxTextures][kMaxLevels];
     __shared__ TrainLevelLut lut;
-    __shared__ uint32_t pool_used;
+    __shared__ uint32_t pool_used, dz_max_bits;
     const uint32_t cell = blockIdx.x;
     const uint32_t begin = cell ? d.bin_next[cell - 1] : 0u, end = d.bin_next[cell];
     if (begin == end) return;                          // uniform over the workgroup
@@ -824,10 +824,43 @@ __global__ void __launch_bounds__(kScatterThreads) k_train_scatter(TrainDesc d, 
         for (uint32_t k = 1; k < 64; k <<= 1) in_use = max(in_use, __shfl_xor(in_use, k));
         if (i == 0u) pool_used = in_use;
     }
+    // The largest |dL/dz| of the cell's samples (as bits: NaN and infinity
+    // above every finite value) sets the windows' fixed-point scale.
+    if (threadIdx.x == 0) dz_max_bits = 0u;
     __syncthreads();
+    {
+        uint32_t mb = 0;
+        for (uint32_t j = begin + threadIdx.x; j < end; j += kScatterThreads) {
+            const uint4 *src = reinterpret_cast<const uint4 *>(d.bin_dz + 12u * (size_t)j);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const uint4 z = src[k];
+                mb = max(mb, max(max(z.x & 0x7FFFFFFFu, z.y & 0x7FFFFFFFu), max(z.z & 0x7FFFFFFFu, z.w & 0x7FFFFFFFu)));
+            }
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) mb = max(mb, (uint32_t)__shfl_xor((int)mb, o));
+        if ((threadIdx.x & 63u) == 0) atomicMax(&dz_max_bits, mb);
+    }
     const uint32_t used = pool_used;
     for (uint32_t e = threadIdx.x; e < used; e += kScatterThreads) pool[e] = 0.0f;
     __syncthreads();
+    // LDS float atomics cost about 40 times integer ones on this GPU, so the
+    // windows sum in 32-bit fixed point: contribution v adds rint(v 2^k),
+    // with 2^k chosen so that the at most nc M of a texel channel (nc samples,
+    // each adding at most M = max |dL/dz| over its taps, whose weights sum to
+    // at most 1) stays below 2^29. Non-finite gradients take float atomics.
+    const uint32_t mbits = dz_max_bits;
+    const bool fixed = mbits < 0x7F800000u;
+    int kexp = 0;
+    if (fixed && mbits != 0u) {
+        int em;
+        frexpf(__uint_as_float(mbits), &em);                  // M < 2^em
+        const uint32_t nc = end - begin;
+        const int en = 32 - __clz(nc);                       // nc < 2^en
+        kexp = min(max(29 - em - en, -120), 120);
+    }
+    const float scale = ldexpf(1.0f, kexp), unscale = ldexpf(1.0f, -kexp);
     for (uint32_t j = begin + threadIdx.x; j < end; j += kScatterThreads) {
         const uint32_t q = d.bin_perm[j];
         const float4 *src = reinterpret_cast<const float4 *>(d.bin_dz + 12u * (size_t)j);
@@ -864,9 +897,15 @@ __global__ void __launch_bounds__(kScatterThreads) k_train_scatter(TrainDesc d, 
                     const uint32_t dx = i & 1 ? dxb : dxa, dy = i & 2 ? dyb : dya;
                     if (W.off != ~0u && dx < W.w && dy < W.h) {
                         float *p = pool + base + 3u * (__umul24(dy, W.w) + dx);
-                        atomicAdd(p + 0, wt * dz[3 * t + 0]);
-                        atomicAdd(p + 1, wt * dz[3 * t + 1]);
-                        atomicAdd(p + 2, wt * dz[3 * t + 2]);
+                        if (fixed) {
+                            uint32_t *pi = reinterpret_cast<uint32_t *>(p);
+#pragma unroll
+                            for (int c = 0; c < 3; ++c)
+                                atomicAdd(pi + c, (uint32_t)(int32_t)rintf(wt * dz[3 * t + c] * scale));
+                        } else {
+#pragma unroll
+                            for (int c = 0; c < 3; ++c) atomicAdd(p + c, wt * dz[3 * t + c]);
+                        }
                     } else {
                         float *gp = reinterpret_cast<float *>(d.g_texels + e.z + y * e.x + x);
                         unsafeAtomicAdd(gp + 0, wt * dz[3 * t + 0]);
@@ -885,7 +924,8 @@ __global__ void __launch_bounds__(kScatterThreads) k_train_scatter(TrainDesc d, 
             const uint4 e = lut[t][l];
             const uint32_t size = 3u * W.w * W.h;
             for (uint32_t i = threadIdx.x; i < size; i += kScatterThreads) {
-                const float v = pool[W.off + i];
+                const float raw = pool[W.off + i];
+                const float v = fixed ? (float)__float_as_int(raw) * unscale : raw;
                 if (v == 0.0f) continue;
                 const uint32_t p = i / 3u, c = i - 3u * p, dy = W.w > 1u ? __umulhi(p, W.div_w) : p, dx = p - dy * W.w;
                 const uint32_t x = (W.x0 + dx) & (e.x - 1u), y = (W.y0 + dy) & (e.y - 1u);
