@@ -103,6 +103,7 @@ __device__ __forceinline__ TexelChan texel_chan(float ea, float eb, float x)
 // position; false for the texels a level below 4x4 does not have.
 struct TexelSite {
     uint32_t ti, b, x, y, tex;      // tex: texel index in the images
+    uint32_t wl;                    // the level's width
     bool valid;
 };
 
@@ -124,6 +125,7 @@ __device__ __forceinline__ TexelSite texel_site(const TrainDesc &d, uint32_t gb,
     s.y = (lb >> __builtin_ctz(bxn)) * 4u + (t >> 2);
     s.valid = s.x < wl && s.y < hl;
     s.tex = tx.tex_off[l] + s.y * wl + s.x;
+    s.wl = wl;
     return s;
 }
 
@@ -133,22 +135,32 @@ __device__ __forceinline__ uint32_t subset_of(const TrainTexDesc &tx, uint32_t b
     return (kTable[kModes * kModeWords + (tx.partitions[b] & 31u)] >> t) & 1u;
 }
 
+// One lane per block row: its four texels (a level narrower than 4 texels
+// keeps the left ones), the block's endpoints and partition read once.
 template <bool STE>
 __global__ void __launch_bounds__(kTrainThreads) k_train_texels(TrainDesc d)
 {
-    const uint32_t total = d.blk_base[d.n_tex] * 16u;
+    const uint32_t total = d.blk_base[d.n_tex] * 4u;
     for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < total; g += gridDim.x * blockDim.x) {
-        const uint32_t t = g & 15u;
-        const TexelSite s = texel_site(d, g >> 4, t);
+        const uint32_t r = g & 3u;
+        const TexelSite s = texel_site(d, g >> 2, 4u * r);
         if (!s.valid) continue;
         const TrainTexDesc &tx = d.tex[s.ti];
-        const uint32_t sub = subset_of(tx, s.b, t);
-        const float *e = tx.endpoints + 12u * s.b;
-        const float x = tx.indices[16u * s.b + t];
-        float w[3];
+        // partition ids are taken modulo 32
+        const uint32_t pmask = kTable[kModes * kModeWords + (tx.partitions[s.b] & 31u)];
+        float e[12];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) w[c] = texel_chan<STE>(e[6u * sub + c], e[6u * sub + 3u + c], x).w;
-        d.texels[s.tex] = make_float4(w[0], w[1], w[2], 0.0f);
+        for (int k = 0; k < 12; ++k) e[k] = tx.endpoints[12u * s.b + k];
+#pragma unroll
+        for (uint32_t i = 0; i < 4; ++i) {
+            if (s.x + i >= s.wl) break;
+            const uint32_t t = 4u * r + i, sub = (pmask >> t) & 1u;
+            const float x = tx.indices[16u * s.b + t];
+            float w[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) w[c] = texel_chan<STE>(sub ? e[6 + c] : e[c], sub ? e[9 + c] : e[3 + c], x).w;
+            d.texels[s.tex + i] = make_float4(w[0], w[1], w[2], 0.0f);
+        }
     }
 }
 
@@ -942,7 +954,7 @@ unsigned grid_for(size_t work, unsigned per_block, unsigned cap)
 
 hipError_t launch_texels(const TrainDesc &d, hipStream_t s)
 {
-    const unsigned grid = grid_for((size_t)d.blk_base[d.n_tex] * 16u, kTrainThreads, 16384);
+    const unsigned grid = grid_for((size_t)d.blk_base[d.n_tex] * 4u, kTrainThreads, 16384);
     if (d.ste) k_train_texels<true><<<grid, kTrainThreads, 0, s>>>(d);
     else k_train_texels<false><<<grid, kTrainThreads, 0, s>>>(d);
     return hipGetLastError();
