@@ -336,11 +336,8 @@ __device__ __forceinline__ void features(const TrainDesc &d, const TrainLevelLut
 
 // The MLP's parameters in LDS, one padded row per neuron: its weights, its
 // bias, zeros (layer 0's inputs padded to 12, the output layer to kMaxOut
-// rows). Every lane reads the same address, so a read is a broadcast; rows
-// are read as 16-byte vectors through a pointer that passes an empty asm per
-// row, so that the optimiser neither hoists the reads out of the query loop
-// nor keeps more than a row of weights live (held in registers instead, the
-// unrolled layers' weights would be spilled).
+// rows). The backward's matrix-core products read a weight (or, for the
+// deltas, its transpose) per lane from these rows.
 template <int H, int NH>
 struct __align__(16) MlpLds {
     float w0[H][16];                          // inputs 0..11, bias at 12
@@ -349,36 +346,6 @@ struct __align__(16) MlpLds {
 };
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef __attribute__((address_space(3))) const f32x4 lds_f32x4;
-
-// Row `row` (N_IN weights then the bias) into registers: w[0..N_IN) weights,
-// w[N_IN] bias. The read is ordered after `after` is computed (the previous
-// row's result), so that the scheduler cannot issue every row's reads at once.
-template <int N_IN>
-__device__ __forceinline__ void lds_row(const float *row, float after, float (&w)[N_IN + 1])
-{
-    uint32_t a = (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) float *)row;
-    asm volatile("" : "+v"(a) : "v"(after));
-    const lds_f32x4 *r = (const lds_f32x4 *)(uintptr_t)a;
-#pragma unroll
-    for (int k = 0; k < (N_IN + 4) / 4; ++k) {
-        const f32x4 v = r[k];
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-            if (4 * k + e <= N_IN) w[4 * k + e] = v[e];
-    }
-}
-
-// Marks v[0..N) as rewritten, N a multiple of 4: every update of them before
-// this point is complete, and (the asm being volatile) no later lds_row reads
-// move above it. Keeps a row-by-row update of a vector row by row.
-template <int N>
-__device__ __forceinline__ void pin(float (&v)[N])
-{
-#pragma unroll
-    for (int k = 0; k < N; k += 4) asm volatile("" : "+v"(v[k]), "+v"(v[k + 1]), "+v"(v[k + 2]), "+v"(v[k + 3]));
-}
-
 // Every thread of the workgroup takes part; synchronises the workgroup.
 template <int H, int NH>
 __device__ __forceinline__ void load_mlp(const TrainDesc &d, MlpLds<H, NH> &m)
@@ -398,35 +365,6 @@ __device__ __forceinline__ void load_mlp(const TrainDesc &d, MlpLds<H, NH> &m)
         m.wl[j][i] = j >= c ? 0.0f : i < H ? P[d.w_off[NH] + j * H + i] : (i == H ? P[d.b_off[NH] + j] : 0.0f);
     }
     __syncthreads();
-}
-
-// The MLP's hidden layers (act[l] = output of hidden layer l), as the
-// backward needs them; the output layer's values are not (its gradient is
-// the caller's dL/dG).
-template <int H, int NH>
-__device__ __forceinline__ void mlp_hidden(const MlpLds<H, NH> &m, const float z[12], float act[NH][H])
-{
-    // inputs past dims[0] are zero (their weights are zero too)
-#pragma unroll
-    for (int j = 0; j < H; ++j) {
-        float w[13];
-        lds_row<12>(m.w0[j], j ? act[0][j - 1] : z[0], w);
-        float acc = w[12];
-#pragma unroll
-        for (int i = 0; i < 12; ++i) acc = fmaf(w[i], z[i], acc);
-        act[0][j] = fmaxf(acc, 0.0f);
-    }
-#pragma unroll
-    for (int l = 1; l < NH; ++l)
-#pragma unroll
-        for (int j = 0; j < H; ++j) {
-            float w[H + 1];
-            lds_row<H>(m.wh[l - 1][j], j ? act[l][j - 1] : act[l - 1][H - 1], w);
-            float acc = w[H];
-#pragma unroll
-            for (int i = 0; i < H; ++i) acc = fmaf(w[i], act[l - 1][i], acc);
-            act[l][j] = fmaxf(acc, 0.0f);
-        }
 }
 
 // The forward with the MLP on the matrix cores (fp32 16x16x4 MFMAs, the
@@ -618,6 +556,37 @@ __global__ void __launch_bounds__(kBinThreads) k_train_bin_scatter(const float *
     if (i < n) perm[hist[bin] + rank] = i;
 }
 
+// Y[s][m] = f(sum over k of Wt(m, k) X[s][k] + bias) for the wave's 64
+// samples s (rows of the LDS arrays X and Y), m < 16 MT, k < 4 KC, on the
+// matrix cores (fp32 16x16x4, K in steps of 4): Wt(m, k) = W[m ldw + k], or
+// W[k ldw + m] when TRANS; the bias W[m ldw + bias_col] when BIAS; f = ReLU
+// when RELU. Lane L supplies Wt(16 mb + L % 16, 4 kc + L / 16) and X[16 grp
+// + L % 16][4 kc + L / 16], and receives rows 4 (L / 16) .. + 3 of sample
+// 16 grp + L % 16.
+template <int MT, int KC, bool TRANS, bool BIAS, bool RELU, int LDX, int LDY>
+__device__ __forceinline__ void rows_product(const float *W, int ldw, int bias_col, const float (*X)[LDX],
+                                             float (*Y)[LDY], uint32_t lane)
+{
+    const uint32_t g = lane >> 4, i16 = lane & 15u;
+#pragma unroll
+    for (int grp = 0; grp < 4; ++grp) {
+#pragma unroll
+        for (int mb = 0; mb < MT; ++mb) {
+            f32x4 acc;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[r] = BIAS ? W[(16 * mb + 4 * g + r) * ldw + bias_col] : 0.0f;
+#pragma unroll
+            for (int kc = 0; kc < KC; ++kc) {
+                const uint32_t m = 16 * mb + i16, k = 4 * kc + g;
+                const float a = TRANS ? W[k * ldw + m] : W[m * ldw + k];
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, X[16 * grp + i16][k], acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) Y[16 * grp + i16][16 * mb + 4 * g + r] = RELU ? fmaxf(acc[r], 0.0f) : acc[r];
+        }
+    }
+}
+
 // Waves per workgroup of the backward: four when its LDS (per-wave rows for
 // the parameter-gradient products, the MLP, the level table) lets two
 // workgroups share a CU -- two waves per SIMD, as its registers allow --
@@ -670,7 +639,24 @@ __global__ void __launch_bounds__((64 * bwd_waves<H, NH>()), 2) k_train_backward
         const float s = live ? queries[3u * q + 2u] : 0.0f;
         float z[12], act[NH][H];
         features(d, lut, u, v, s, z);
-        mlp_hidden<H, NH>(mlp, z, act);
+        // the hidden layers on the matrix cores, layer by layer through the
+        // wave's LDS rows (inputs in one array, outputs in the other)
+#pragma unroll
+        for (int i = 0; i < 12; ++i) a[lane][i] = z[i];
+        wave_sync_lds();
+        rows_product<T, 3, false, true, true>(&mlp.w0[0][0], 16, 12, a, dl, lane);
+        wave_sync_lds();
+#pragma unroll
+        for (int i = 0; i < H; ++i) act[0][i] = dl[lane][i];
+#pragma unroll
+        for (int l = 1; l < NH; ++l) {
+            if (l & 1) rows_product<T, H / 4, false, true, true>(&mlp.wh[l - 1][0][0], H + 4, H, dl, a, lane);
+            else rows_product<T, H / 4, false, true, true>(&mlp.wh[l - 1][0][0], H + 4, H, a, dl, lane);
+            wave_sync_lds();
+#pragma unroll
+            for (int i = 0; i < H; ++i) act[l][i] = l & 1 ? a[lane][i] : dl[lane][i];
+            wave_sync_lds();
+        }
         float delta[kTrainMaxHidden];
 #pragma unroll
         for (int j = 0; j < kTrainMaxHidden; ++j)
@@ -691,31 +677,15 @@ __global__ void __launch_bounds__((64 * bwd_waves<H, NH>()), 2) k_train_backward
             // g = W_{l+1}^T delta, summed over the rows j in order; the rows
             // of W_{l+1} are read whole (the output layer's past c are zero,
             // and so are the deltas there)
+            // (on the matrix cores: the deltas are dl's rows, the products
+            // land in a's rows, which the parameter sums above have read)
+            if (l == NH - 1) rows_product<T, kMaxOut / 4, true, false, false>(&mlp.wl[0][0], H + 4, 0, dl, a, lane);
+            else rows_product<T, H / 4, true, false, false>(&mlp.wh[l][0][0], H + 4, 0, dl, a, lane);
+            wave_sync_lds();
             float g[H];
 #pragma unroll
-            for (int i = 0; i < H; ++i) g[i] = 0.0f;
-            if (l == NH - 1) {
-#pragma unroll
-                for (int j = 0; j < kMaxOut; ++j)
-                    if ((uint32_t)j < c) {
-                        float w[H + 1];
-                        lds_row<H>(mlp.wl[j], g[H - 1], w);
-#pragma unroll
-                        for (int i = 0; i < H; ++i) g[i] = fmaf(w[i], delta[j], g[i]);
-                        pin(g);
-                    }
-            } else {
-#pragma unroll
-                for (int j = 0; j < H; ++j) {
-                    float w[H + 1];
-                    lds_row<H>(mlp.wh[l][j], g[H - 1], w);
-#pragma unroll
-                    for (int i = 0; i < H; ++i) g[i] = fmaf(w[i], delta[j], g[i]);
-                    pin(g);
-                }
-            }
-#pragma unroll
-            for (int i = 0; i < H; ++i) g[i] = act[l][i] > 0.0f ? g[i] : 0.0f;
+            for (int i = 0; i < H; ++i) g[i] = act[l][i] > 0.0f ? a[lane][i] : 0.0f;
+            wave_sync_lds();
 #pragma unroll
             for (int i = 0; i < H; ++i) delta[i] = g[i];
             // parameters of layer l: inputs are act[l - 1] (or z), outputs delta
@@ -735,18 +705,14 @@ __global__ void __launch_bounds__((64 * bwd_waves<H, NH>()), 2) k_train_backward
             else accumulate(gh[l > 0 ? l - 1 : 0], a, dl, lane);
             wave_sync_lds();
         }
-        // dL/dz = W_0^T delta
+        // dL/dz = W_0^T delta (rows 12 .. 15 of the product, from the bias
+        // column and the padding, are not used)
+        rows_product<1, H / 4, true, false, false>(&mlp.w0[0][0], 16, 0, dl, a, lane);
+        wave_sync_lds();
         float dz[12];
 #pragma unroll
-        for (int i = 0; i < 12; ++i) dz[i] = 0.0f;
-#pragma unroll
-        for (int j = 0; j < H; ++j) {
-            float w[13];
-            lds_row<12>(mlp.w0[j], dz[11], w);
-#pragma unroll
-            for (int i = 0; i < 12; ++i) dz[i] = fmaf(w[i], delta[j], dz[i]);
-            pin(dz);
-        }
+        for (int i = 0; i < 12; ++i) dz[i] = a[lane][i];
+        wave_sync_lds();
         // dL/dz in the sorted order, for the scatter
         if (live) {
             float4 *dst = reinterpret_cast<float4 *>(d.bin_dz + 12u * (size_t)slot);
