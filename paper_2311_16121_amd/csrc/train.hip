@@ -480,6 +480,11 @@ __device__ __forceinline__ void flush(const LayerGrad<MT, NT> &g, float *gw, flo
 // gradient lines update them while the lines sit in one L2.
 
 constexpr int kBinThreads = 1024;
+// samples a thread of the count and placement kernels takes: a workgroup's
+// histogram then covers 16K samples, so that fewer cells of it reach memory
+// (one atomic per touched cell and workgroup)
+constexpr int kBinPerThread = 16;
+constexpr uint32_t kBinPerGroup = kBinThreads * kBinPerThread;
 
 // A query's cell: its wrapped (u, v) on the kTrainBinSide grid (NaN and
 // infinities land in cell 0), numbered along a Z-order curve.
@@ -495,14 +500,18 @@ __device__ __forceinline__ uint32_t bin_of(float u, float v)
     return z;
 }
 
-// count[cell] += samples of the cell; one sample per thread, a histogram in LDS per workgroup
+// count[cell] += samples of the cell; kBinPerGroup samples per workgroup
+// (sample blockIdx * kBinPerGroup + k * kBinThreads + threadIdx), a histogram in LDS
 __global__ void __launch_bounds__(kBinThreads) k_train_bin_count(const float *queries, uint32_t n, uint32_t *count)
 {
     __shared__ uint32_t hist[kTrainBins];
     for (uint32_t b = threadIdx.x; b < kTrainBins; b += kBinThreads) hist[b] = 0u;
     __syncthreads();
-    const uint32_t i = blockIdx.x * kBinThreads + threadIdx.x;
-    if (i < n) atomicAdd(&hist[bin_of(queries[3u * i], queries[3u * i + 1u])], 1u);
+#pragma unroll 4
+    for (uint32_t k = 0; k < (uint32_t)kBinPerThread; ++k) {
+        const uint32_t i = blockIdx.x * kBinPerGroup + k * kBinThreads + threadIdx.x;
+        if (i < n) atomicAdd(&hist[bin_of(queries[3u * i], queries[3u * i + 1u])], 1u);
+    }
     __syncthreads();
     for (uint32_t b = threadIdx.x; b < kTrainBins; b += kBinThreads)
         if (hist[b]) atomicAdd(&count[b], hist[b]);
@@ -538,22 +547,31 @@ __global__ void __launch_bounds__(kBinThreads) k_train_bin_scan(const uint32_t *
     }
 }
 
-// perm[next[cell]++] = sample: each workgroup ranks its samples per cell in
-// LDS, then reserves one run per cell it holds
+// perm[next[cell]++] = sample: each workgroup ranks its kBinPerGroup samples
+// (as k_train_bin_count takes them) per cell in LDS, then reserves one run per
+// cell it holds
 __global__ void __launch_bounds__(kBinThreads) k_train_bin_scatter(const float *queries, uint32_t n, uint32_t *next,
                                                                    uint32_t *perm)
 {
     __shared__ uint32_t hist[kTrainBins];
     for (uint32_t b = threadIdx.x; b < kTrainBins; b += kBinThreads) hist[b] = 0u;
     __syncthreads();
-    const uint32_t i = blockIdx.x * kBinThreads + threadIdx.x;
-    const uint32_t bin = i < n ? bin_of(queries[3u * i], queries[3u * i + 1u]) : 0u;
-    const uint32_t rank = i < n ? atomicAdd(&hist[bin], 1u) : 0u;
+    uint32_t bin[kBinPerThread], rank[kBinPerThread];
+#pragma unroll
+    for (uint32_t k = 0; k < (uint32_t)kBinPerThread; ++k) {
+        const uint32_t i = blockIdx.x * kBinPerGroup + k * kBinThreads + threadIdx.x;
+        bin[k] = i < n ? bin_of(queries[3u * i], queries[3u * i + 1u]) : 0u;
+        rank[k] = i < n ? atomicAdd(&hist[bin[k]], 1u) : 0u;
+    }
     __syncthreads();
     for (uint32_t b = threadIdx.x; b < kTrainBins; b += kBinThreads)
         if (hist[b]) hist[b] = atomicAdd(&next[b], hist[b]);
     __syncthreads();
-    if (i < n) perm[hist[bin] + rank] = i;
+#pragma unroll
+    for (uint32_t k = 0; k < (uint32_t)kBinPerThread; ++k) {
+        const uint32_t i = blockIdx.x * kBinPerGroup + k * kBinThreads + threadIdx.x;
+        if (i < n) perm[hist[bin[k]] + rank[k]] = i;
+    }
 }
 
 // Y[s][m] = f(sum over k of Wt(m, k) X[s][k] + bias) for the wave's 64
@@ -993,7 +1011,7 @@ hipError_t launch_train_backward(const TrainDesc &d, const float *queries, size_
     for (size_t off = 0; off < n; off += kTrainBinBatch) {
         const uint32_t m = (uint32_t)std::min(n - off, (size_t)kTrainBinBatch);
         const float *q = queries + 3 * off;
-        const unsigned bins = (m + kBinThreads - 1) / kBinThreads;
+        const unsigned bins = (m + kBinPerGroup - 1) / kBinPerGroup;
         // (the counts are cleared as floats: 0.0f is all zero bits)
         k_train_zero<<<8, 256, 0, s>>>(reinterpret_cast<float *>(d.bin_count), kTrainBins);
         k_train_bin_count<<<bins, kBinThreads, 0, s>>>(q, m, d.bin_count);
