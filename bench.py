@@ -369,7 +369,7 @@ def bench_train(args):
 
     def step():
         out = bcf.train_decode(geo, leaves[:4], leaves[4:], w, qd)
-        loss = torch.mean((out - target) ** 2)
+        loss = torch.nn.functional.mse_loss(out, target)
         opt.zero_grad(set_to_none=False)
         loss.backward()
         opt.step()
