@@ -370,7 +370,7 @@ def bench_train(args):
     def step():
         out = bcf.train_decode(geo, leaves[:4], leaves[4:], w, qd)
         loss = torch.nn.functional.mse_loss(out, target)
-        opt.zero_grad(set_to_none=False)
+        opt.zero_grad()
         loss.backward()
         opt.step()
         return loss
